@@ -1,0 +1,456 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names what it pins. None re-uses the oracle's own formulas: the
+1-D rules come from scipy, the basis and the integrals from an exact
+polynomial integrator with a Vandermonde basis (exact_poly), and the rest
+are closed forms and invariants.
+"""
+from math import factorial
+
+import numpy as np
+import pytest
+from scipy.special import roots_jacobi
+
+import exact_poly as X
+from paper_1407_0904_amd import inputs as I
+
+
+def nsc(d, p):
+    return I.n_scalar_dofs(d, p)
+
+
+def rational_cell(d, rng):
+    """A positively oriented cell with dyadic vertex coordinates."""
+    while True:
+        v = rng.integers(-8, 9, size=(d + 1, d)) / 8.0
+        det = np.linalg.det((v[1:] - v[0]).T)
+        if abs(det) > 0.05:
+            if det < 0:
+                v[[-2, -1]] = v[[-1, -2]]
+            return v
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+# ---------------------------------------------------------------- quadrature
+
+@pytest.mark.parametrize("m", range(1, 8))
+@pytest.mark.parametrize("alpha", [0, 1, 2])
+def test_gauss_jacobi_matches_scipy(oracle, m, alpha):
+    """1-D Gauss-Jacobi rules equal scipy's (a different algorithm)."""
+    x, w = oracle.gauss_jacobi(m, alpha)
+    xs, ws = roots_jacobi(m, alpha, 0)
+    np.testing.assert_allclose(x, (xs + 1) / 2, rtol=0, atol=2e-15)
+    np.testing.assert_allclose(w, ws / 2 ** (alpha + 1), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("q", range(0, 11))
+def test_simplex_rule_exact_on_monomials(oracle, d, q):
+    """int_ref X^a Y^b (Z^c) = a! b! c! / (a+b+c+d)! for total degree <= q."""
+    Xq, W, _, _ = oracle.tabulate(d, 1, q)
+    m = (q + 2) // 2
+    assert W.shape[0] == m ** d
+    assert np.all(W > 0)
+    assert abs(W.sum() - 1.0 / factorial(d)) < 1e-15
+    for e in X.monomials(d, q):
+        exact = np.prod([factorial(k) for k in e]) / factorial(sum(e) + d)
+        got = np.sum(W * np.prod(Xq ** np.array(e), axis=1))
+        assert abs(got - exact) <= 1e-14 * max(exact, 1e-3), (e, got, exact)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("q", [2, 4, 5, 8])
+def test_simplex_rule_is_collapsed_product(oracle, d, q):
+    """The rule is Stroud's conical product of scipy's 1-D rules, u outermost."""
+    Xq, W, _, _ = oracle.tabulate(d, 1, q)
+    m = (q + 2) // 2
+
+    def r(alpha):
+        x, w = roots_jacobi(m, alpha, 0)
+        return (x + 1) / 2, w / 2 ** (alpha + 1)
+
+    if d == 2:
+        (u, wu), (v, wv) = r(1), r(0)
+        pts = [(a, (1 - a) * b) for a in u for b in v]
+        wts = [x * y for x in wu for y in wv]
+    else:
+        (u, wu), (v, wv), (t, wt) = r(2), r(1), r(0)
+        pts = [(a, (1 - a) * b, (1 - a) * (1 - b) * c) for a in u for b in v for c in t]
+        wts = [x * y * z for x in wu for y in wv for z in wt]
+    np.testing.assert_allclose(Xq, np.array(pts), atol=1e-15)
+    np.testing.assert_allclose(W, np.array(wts), rtol=1e-13)
+
+
+def test_paper_point_counts(oracle):
+    """Listing 1 has W[3] for a degree-2 triangle rule and Listing 2 W[5] for
+    the P1 Burgers tetrahedron; the collapsed rule uses m^d points instead
+    (4 and 8). Only the exactness degree is shared; pinned here as a reading."""
+    assert oracle.tabulate(2, 1, 2)[1].shape[0] == 4
+    assert oracle.tabulate(3, 1, 3)[1].shape[0] == 8
+
+
+# ---------------------------------------------------------------- basis
+
+@pytest.mark.parametrize("d,p", [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3), (3, 4)])
+def test_basis_nodal_and_partition_of_unity(oracle, d, p):
+    nodes = X.lagrange_nodes(d, p)
+    assert nodes.shape[0] == nsc(d, p)
+    phi, dphi = oracle.basis_at(d, p, nodes)
+    np.testing.assert_allclose(phi, np.eye(nodes.shape[0]), atol=1e-13)
+    rng = np.random.default_rng(p)
+    pts = rng.dirichlet(np.ones(d + 1), size=20)[:, 1:]
+    phi, dphi = oracle.basis_at(d, p, pts)
+    np.testing.assert_allclose(phi.sum(axis=1), 1.0, atol=1e-13)
+    np.testing.assert_allclose(dphi.sum(axis=2), 0.0, atol=1e-12)
+    # values and gradients equal the Vandermonde-built basis
+    B = X.lagrange_basis(d, p)
+    for a, b in enumerate(B):
+        np.testing.assert_allclose(phi[:, a], b(pts), atol=1e-12)
+        for j in range(d):
+            np.testing.assert_allclose(dphi[j, :, a], b.deriv(j)(pts), atol=1e-11)
+
+
+def test_tabulate_matches_basis_at(oracle):
+    Xq, W, B, D = oracle.tabulate(3, 2, 4)
+    phi, dphi = oracle.basis_at(3, 2, Xq)
+    np.testing.assert_array_equal(B, phi)
+    np.testing.assert_array_equal(D, dphi)
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_p1_triangle_mass_closed_form(oracle):
+    """|T|/12 [[2,1,1],[1,2,1],[1,1,2]] (the P1 triangle mass matrix)."""
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        v = rng.uniform(-1, 1, size=(3, 2))
+        if np.linalg.det((v[1:] - v[0]).T) < 0:
+            v[[1, 2]] = v[[2, 1]]
+        area = 0.5 * abs(np.linalg.det((v[1:] - v[0]).T))
+        m = I.single_cell_mesh(2, v)
+        A = oracle.assemble("mass", m, 1)[0]
+        np.testing.assert_allclose(A, area / 12 * np.array([[2, 1, 1], [1, 2, 1], [1, 1, 2]]), rtol=1e-14)
+
+
+def test_p1_tet_mass_closed_form(oracle):
+    """|T|/20 (1 + delta_ab)."""
+    v = np.array([[0.1, 0.0, 0.2], [1.0, 0.1, 0.0], [0.2, 0.9, 0.1], [0.0, 0.3, 1.1]])
+    vol = abs(np.linalg.det((v[1:] - v[0]).T)) / 6
+    A = oracle.assemble("mass", I.single_cell_mesh(3, v), 1)[0]
+    np.testing.assert_allclose(A, vol / 20 * (np.ones((4, 4)) + np.eye(4)), rtol=1e-14)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_p1_stiffness_closed_form(oracle, d):
+    """K = |T| G G^T with G the constant barycentric gradients (from a solve)."""
+    rng = np.random.default_rng(7 + d)
+    v = rational_cell(d, rng)
+    Mx = np.hstack([np.ones((d + 1, 1)), v])          # lambda_a(x) = c_a + g_a . x
+    coef = np.linalg.solve(Mx, np.eye(d + 1))          # column a -> (c_a, g_a)
+    G = coef[1:, :].T
+    vol = abs(np.linalg.det((v[1:] - v[0]).T)) / factorial(d)
+    zero = I.Field(values=np.zeros((d + 1, 1)), cell_to_dof=np.arange(d + 1, dtype=np.int32)[None], degree=1, ncomp=1)
+    A = oracle.assemble("helmholtz", I.single_cell_mesh(d, v), 1, fields=[zero])[0]
+    np.testing.assert_allclose(A, vol * G @ G.T, rtol=1e-13, atol=1e-14)
+
+
+def test_listing1_helmholtz_expression(oracle):
+    """Listing 1 (section 2): A[j][k] += (Y Y + (K1 X_D10 + K3 X_D01)(...) +
+    (K0 X_D10 + K2 X_D01)(...)) det W[i], with K = J^-1 row-major
+    (K0 K1 / K2 K3). Evaluated with a 3-point degree-2 rule (edge midpoints,
+    weight 1/6), which integrates this P1 integrand exactly."""
+    v = np.array([[0.2, 0.1], [1.3, 0.4], [0.5, 1.2]])
+    Jm = (v[1:] - v[0]).T
+    det = np.linalg.det(Jm)
+    K0, K1, K2, K3 = np.linalg.inv(Jm).reshape(-1)
+    pts = np.array([[0.5, 0.0], [0.5, 0.5], [0.0, 0.5]])
+    W = np.full(3, 1.0 / 6.0)
+    Y = np.stack([1 - pts[:, 0] - pts[:, 1], pts[:, 0], pts[:, 1]], axis=1)
+    X_D10 = np.tile([-1.0, 1.0, 0.0], (3, 1))
+    X_D01 = np.tile([-1.0, 0.0, 1.0], (3, 1))
+    A = np.zeros((3, 3))
+    for i in range(3):
+        for j in range(3):
+            for k in range(3):
+                A[j][k] += ((Y[i][k] * Y[i][j]
+                             + ((K1 * X_D10[i][k] + K3 * X_D01[i][k]) * (K1 * X_D10[i][j] + K3 * X_D01[i][j]))
+                             + ((K0 * X_D10[i][k] + K2 * X_D01[i][k]) * (K0 * X_D10[i][j] + K2 * X_D01[i][j])))
+                            * det * W[i])
+    got = oracle.assemble("helmholtz", I.single_cell_mesh(2, v), 1)[0]
+    np.testing.assert_allclose(got, A, rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------- exact polynomial integrals
+
+@pytest.mark.parametrize("d,p", [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3)])
+def test_mass_and_helmholtz_exact(oracle, d, p):
+    """f = 1: mass and Helmholtz at degree 2p are exact; compare with exact integrals."""
+    rng = np.random.default_rng(10 * d + p)
+    v = rational_cell(d, rng)
+    cell = X.Cell(v)
+    m = I.single_cell_mesh(d, v)
+    Am = oracle.assemble("mass", m, p)[0]
+    Ah = oracle.assemble("helmholtz", m, p)[0]
+    assert rel(Am, X.mass(cell, p)) < 1e-12
+    assert rel(Ah, X.mass(cell, p, stiff=True)) < 1e-12
+
+
+@pytest.mark.parametrize("d,p,pf", [(2, 1, 1), (2, 2, 2), (3, 2, 2), (3, 1, 1), (2, 3, 1)])
+def test_coefficient_mass_exact(oracle, d, p, pf):
+    """int f phi_a phi_b with f in P_pf, integrated exactly (quad degree 2p + pf)."""
+    rng = np.random.default_rng(5 + p + 3 * pf)
+    v = rational_cell(d, rng)
+    nf = nsc(d, pf)
+    fv = rng.uniform(0.5, 1.5, size=(nf, 1))
+    fld = I.Field(values=fv, cell_to_dof=np.arange(nf, dtype=np.int32)[None], degree=pf, ncomp=1)
+    f = X.field_poly(d, pf, fv)[0]
+    m = I.single_cell_mesh(d, v)
+    cell = X.Cell(v)
+    for form, stiff in (("mass", False), ("helmholtz", True)):
+        got = oracle.assemble(form, m, p, quad_degree=2 * p + pf, fields=[fld])[0]
+        assert rel(got, X.mass(cell, p, f=f, stiff=stiff)) < 1e-12
+
+
+@pytest.mark.parametrize("d,p", [(2, 1), (3, 1), (3, 2), (2, 2)])
+def test_elasticity_exact(oracle, d, p):
+    """Elasticity with P1 Lame fields against the index form, integrated exactly."""
+    rng = np.random.default_rng(20 + 3 * d + p)
+    v = rational_cell(d, rng)
+    mu_v = rng.uniform(1, 10, size=(d + 1, 1))
+    lm_v = rng.uniform(1, 10, size=(d + 1, 1))
+    c2d = np.arange(d + 1, dtype=np.int32)[None]
+    flds = [I.Field(mu_v, c2d, 1, 1), I.Field(lm_v, c2d, 1, 1)]
+    got = oracle.assemble("elasticity", I.single_cell_mesh(d, v), p, quad_degree=2 * p - 1, fields=flds)[0]
+    want = X.elasticity(X.Cell(v), p, X.field_poly(d, 1, mu_v)[0], X.field_poly(d, 1, lm_v)[0])
+    assert rel(got, want) < 1e-12
+    assert rel(got, got.T) < 1e-13
+
+
+@pytest.mark.parametrize("d,p,pw", [(2, 1, 1), (3, 1, 1), (3, 2, 2), (2, 2, 2)])
+def test_burgers_exact(oracle, d, p, pw):
+    """Burgers Jacobian with a polynomial state w, integrated exactly (degree 2p + pw - 1)."""
+    rng = np.random.default_rng(30 + 3 * d + p)
+    v = rational_cell(d, rng)
+    nw = nsc(d, pw)
+    wv = rng.uniform(-1, 1, size=(nw, d))
+    fld = I.Field(wv, np.arange(nw, dtype=np.int32)[None], pw, d)
+    nu, inv_dt = 0.7, 1.9
+    got = oracle.assemble("burgers", I.single_cell_mesh(d, v), p, quad_degree=2 * p + pw,
+                          fields=[fld], constants=[nu, inv_dt])[0]
+    want = X.burgers(X.Cell(v), p, X.field_poly(d, pw, wv), nu, inv_dt)
+    assert rel(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("d,p", [(3, 1), (2, 2), (3, 2)])
+def test_svk_exact(oracle, d, p):
+    """SVK energy, residual and Jacobian against exact integration (degree 2p is exact)."""
+    rng = np.random.default_rng(40 + d + p)
+    v = rational_cell(d, rng)
+    n = nsc(d, p)
+    uv = rng.normal(0, 0.2, size=(n, d))
+    fld = I.Field(uv, np.arange(n, dtype=np.int32)[None], p, d)
+    mu, lm = 1.3, 0.8
+    m = I.single_cell_mesh(d, v)
+    e, r, j = X.svk(X.Cell(v), p, X.field_poly(d, p, uv), mu, lm)
+    kw = dict(fields=[fld], constants=[mu, lm])
+    assert rel(oracle.assemble("svk_energy", m, p, **kw), np.array([e])) < 1e-12
+    assert rel(oracle.assemble("svk_residual", m, p, **kw)[0], r) < 1e-12
+    got = oracle.assemble("svk_jacobian", m, p, **kw)[0]
+    assert rel(got, j) < 1e-12
+    assert rel(got, got.T) < 1e-13
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_mass_sum_and_stiffness_rows(oracle):
+    """sum_ab M_ab = int f (partition of unity), stiffness rows sum to 0, symmetry."""
+    w = I.workload("helmholtz_p2_tet", n=3)
+    f = w.fields[0]
+    M = oracle.assemble("mass", w.mesh, 2, 4, fields=[f])
+    assert rel(M, np.transpose(M, (0, 2, 1))) < 1e-14
+    zero = I.Field(np.zeros_like(f.values), f.cell_to_dof, 2, 1)
+    K = oracle.assemble("helmholtz", w.mesh, 2, 4, fields=[zero])
+    assert np.max(np.abs(K.sum(axis=2))) < 1e-12 * np.max(np.abs(K))
+    # int f for P2 f on a tetrahedron: vertex dofs weigh -|T|/20, edge dofs |T|/5
+    c = w.mesh.coords[w.mesh.cells]
+    vol = np.abs(np.linalg.det(np.transpose(c[:, 1:] - c[:, :1], (0, 2, 1)))) / 6
+    fl = f.values[f.cell_to_dof, 0]
+    intf = vol * (-fl[:, :4].sum(1) / 20 + fl[:, 4:].sum(1) / 5)
+    np.testing.assert_allclose(M.sum(axis=(1, 2)), intf, rtol=1e-12)
+
+
+@pytest.mark.parametrize("d,n", [(2, 4), (3, 2)])
+def test_tiny_mesh_total_mass(oracle, d, n):
+    """Sum over cells of sum_ab M_ab = measure of the unit square / cube (f = 1)."""
+    mesh = I.make_mesh(d, n, 0.2, np.random.default_rng(1))
+    for p in (1, 2, 3):
+        M = oracle.assemble("mass", mesh, p)
+        assert abs(M.sum() - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_elasticity_rigid_modes(oracle, p):
+    """A r = 0 for the 6 rigid motions (interpolated exactly by P1 and P2)."""
+    w = I.workload("elasticity_p2_tet", n=2)
+    A = oracle.assemble("elasticity", w.mesh, p, fields=w.fields)
+    nodes = X.lagrange_nodes(3, p)
+    for e in range(0, w.mesh.ncells, 7):
+        v = w.mesh.coords[w.mesh.cells[e]]
+        x = v[0] + nodes @ (v[1:] - v[0])           # physical node positions
+        n = x.shape[0]
+        modes = []
+        for c in range(3):
+            r = np.zeros((3, n)); r[c] = 1.0; modes.append(r.reshape(-1))
+        for (i, j) in ((0, 1), (0, 2), (1, 2)):
+            r = np.zeros((3, n)); r[i] = -x[:, j]; r[j] = x[:, i]; modes.append(r.reshape(-1))
+        for r in modes:
+            assert np.max(np.abs(A[e] @ r)) < 1e-12 * np.max(np.abs(A[e]))
+
+
+def test_burgers_zero_state_is_block_diagonal(oracle):
+    """w = 0: Burgers = blockdiag((1/dt) M + nu K) for each component."""
+    w = I.workload("burgers_p2_tet", n=2)
+    nu, inv_dt = 0.3, 2.0
+    zero = I.Field(np.zeros_like(w.fields[0].values), w.fields[0].cell_to_dof, 2, 3)
+    A = oracle.assemble("burgers", w.mesh, 2, 5, fields=[zero], constants=[nu, inv_dt])
+    M = oracle.assemble("mass", w.mesh, 2, 5)
+    H = oracle.assemble("helmholtz", w.mesh, 2, 5)
+    Kst = H - M
+    n = 10
+    for c1 in range(3):
+        for c2 in range(3):
+            blk = A[:, c1 * n:(c1 + 1) * n, c2 * n:(c2 + 1) * n]
+            want = inv_dt * M + nu * Kst if c1 == c2 else 0 * M
+            assert np.max(np.abs(blk - want)) < 1e-13 * np.max(np.abs(A))
+
+
+def test_svk_at_zero_is_elasticity(oracle):
+    """u = 0: energy 0, residual 0, Jacobian = elasticity with the same constant mu, lambda."""
+    w = I.workload("svk_p2_tet", n=2)
+    zero = I.Field(np.zeros_like(w.fields[0].values), w.fields[0].cell_to_dof, 2, 3)
+    kw = dict(fields=[zero], constants=[1.7, 0.6])
+    assert np.max(np.abs(oracle.assemble("svk_energy", w.mesh, 2, **kw))) == 0.0
+    assert np.max(np.abs(oracle.assemble("svk_residual", w.mesh, 2, **kw))) < 1e-15
+    Jm = oracle.assemble("svk_jacobian", w.mesh, 2, **kw)
+    El = oracle.assemble("elasticity", w.mesh, 2, constants=[1.7, 0.6])
+    assert rel(Jm, El) < 1e-13
+
+
+def test_svk_frame_indifference(oracle):
+    """u = (Q - I) x with Q a finite rotation: energy 0 and residual 0."""
+    w = I.workload("svk_p2_tet", n=2)
+    t = 0.7
+    Q = np.array([[np.cos(t), -np.sin(t), 0], [np.sin(t), np.cos(t), 0], [0, 0, 1.0]])
+    nodes = X.lagrange_nodes(3, 2)
+    ncell = w.mesh.ncells
+    uv = np.zeros((ncell, 10, 3))
+    for e in range(ncell):
+        v = w.mesh.coords[w.mesh.cells[e]]
+        x = v[0] + nodes @ (v[1:] - v[0])
+        uv[e] = x @ (Q - np.eye(3)).T
+    fld = I.Field(uv, None, 2, 3)
+    kw = dict(fields=[fld], constants=[1.0, 1.0])
+    assert np.max(np.abs(oracle.assemble("svk_energy", w.mesh, 2, **kw))) < 1e-14
+    assert np.max(np.abs(oracle.assemble("svk_residual", w.mesh, 2, **kw))) < 1e-13
+
+
+@pytest.mark.parametrize("form,p", [("mass", 2), ("helmholtz", 3)])
+def test_affine_invariance(oracle, form, p):
+    """Translation leaves A unchanged; rotation too (scalar forms); scaling by s
+    multiplies mass by s^d and stiffness by s^(d-2)."""
+    rng = np.random.default_rng(9)
+    v = rng.uniform(-1, 1, size=(4, 3))
+    if np.linalg.det((v[1:] - v[0]).T) < 0:
+        v[[2, 3]] = v[[3, 2]]
+    A0 = oracle.assemble(form, I.single_cell_mesh(3, v), p)[0]
+    At = oracle.assemble(form, I.single_cell_mesh(3, v + np.array([3.0, -2.0, 5.0])), p)[0]
+    assert rel(At, A0) < 1e-12
+    a = 0.9
+    R = np.array([[1, 0, 0], [0, np.cos(a), -np.sin(a)], [0, np.sin(a), np.cos(a)]])
+    Ar = oracle.assemble(form, I.single_cell_mesh(3, v @ R.T), p)[0]
+    assert rel(Ar, A0) < 1e-12
+    s = 2.5
+    M0 = oracle.assemble("mass", I.single_cell_mesh(3, v), p)[0]
+    Ms = oracle.assemble("mass", I.single_cell_mesh(3, s * v), p)[0]
+    assert rel(Ms, s ** 3 * M0) < 1e-13
+    K0 = oracle.assemble("helmholtz", I.single_cell_mesh(3, v), p)[0] - M0
+    Ks = oracle.assemble("helmholtz", I.single_cell_mesh(3, s * v), p)[0] - Ms
+    assert rel(Ks, s * K0) < 1e-12
+
+
+def test_degenerate_cell_reports(oracle):
+    v = np.array([[0.0, 0.0], [1.0, 1.0], [2.0, 2.0]])
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.assemble("mass", I.single_cell_mesh(2, v), 1)
+    assert ei.value.code == 4
+    v = np.array([[0.0, 0.0], [1.0, np.nan], [0.0, 1.0]])
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.assemble("mass", I.single_cell_mesh(2, v), 1)
+    assert ei.value.code == 4
+
+
+# ---------------------------------------------------------------- adjoint (complex step)
+
+def _central_fd(fun, x, h=1e-6):
+    g = np.zeros_like(x)
+    flat = x.reshape(-1)
+    gf = g.reshape(-1)
+    for i in range(flat.size):
+        old = flat[i]
+        flat[i] = old + h; fp = fun()
+        flat[i] = old - h; fm = fun()
+        flat[i] = old
+        gf[i] = (fp - fm) / (2 * h)
+    return g
+
+
+def test_adjoint_complex_step_vs_central_fd(oracle):
+    """Complex-step gradients of S = sum lam^T A u equal central differences (h = 1e-6)."""
+    w = I.workload("elasticity_p2_tet", n=1)
+    mesh, flds = w.mesh, w.fields
+    S, gc, gf = oracle.adjoint("elasticity", mesh, 2, fields=flds, lam=w.lam, u=w.u)
+
+    def S_of():
+        A = oracle.assemble("elasticity", mesh, 2, fields=flds)
+        return float(np.einsum("ei,eij,ej->", w.lam, A, w.u))
+
+    assert abs(S - S_of()) < 1e-12 * abs(S)
+    fd = _central_fd(S_of, mesh.coords)
+    assert rel(gc, fd) < 1e-6
+    for k in range(2):
+        fdk = _central_fd(S_of, flds[k].values)
+        assert rel(gf[k], fdk) < 1e-6
+
+
+def test_adjoint_invariants(oracle):
+    """Translation: sum_v dS/dx_v = 0. Euler homogeneity (3-D elasticity,
+    coefficient dofs fixed): sum_v x_v . dS/dx_v = S. Linearity in (mu, lambda):
+    sum mu_r dS/dmu_r + sum lambda_r dS/dlambda_r = S."""
+    w = I.workload("elasticity_p2_tet", n=2)
+    S, gc, gf = oracle.adjoint("elasticity", w.mesh, 2, fields=w.fields, lam=w.lam, u=w.u)
+    assert np.max(np.abs(gc.sum(axis=0))) < 1e-10 * np.max(np.abs(gc))
+    assert abs(np.sum(w.mesh.coords * gc) - S) < 1e-10 * np.max(np.abs(gc))
+    lin = np.sum(w.fields[0].values * gf[0]) + np.sum(w.fields[1].values * gf[1])
+    assert abs(lin - S) < 1e-11 * abs(S)
+
+
+def test_svk_residual_is_energy_gradient(oracle):
+    """R = dPi/du (complex step on the energy) and J = dR/du (on the residual)."""
+    rng = np.random.default_rng(4)
+    mesh = I.random_cells(3, 2, rng)
+    n = 10
+    uv = rng.normal(0, 0.05, size=(2, n, 3))
+    fld = I.Field(uv, None, 2, 3)
+    kw = dict(fields=[fld], constants=[1.1, 0.9])
+    R = oracle.assemble("svk_residual", mesh, 2, **kw)
+    _, _, gf = oracle.adjoint("svk_energy", mesh, 2, **kw)
+    # gradient layout [E][n][3] vs residual layout [E][3 n] (component-blocked)
+    assert rel(np.transpose(gf[0], (0, 2, 1)).reshape(2, -1), R) < 1e-12
+    Jm = oracle.assemble("svk_jacobian", mesh, 2, **kw)
+    for i in (0, 7, 19, 25):
+        lam = np.zeros((2, 3 * n)); lam[:, i] = 1.0
+        _, _, gr = oracle.adjoint("svk_residual", mesh, 2, lam=lam, **kw)
+        assert rel(np.transpose(gr[0], (0, 2, 1)).reshape(2, -1), Jm[:, i, :]) < 1e-12
