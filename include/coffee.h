@@ -1,0 +1,174 @@
+/*
+ * coffee.h - C ABI of libcoffee, finite element local assembly on MI355X.
+ *
+ * Local assembly (paper, section 2 and Fig. 1) evaluates, for every cell of
+ * a mesh, the element tensor of a variational form by mapping the cell to a
+ * reference simplex, evaluating basis functions and coefficient fields at
+ * quadrature points and summing integrand * |det J| * weight. The paper's
+ * per-cell contract (Fig. 1; Listing 1 `helmholtz(double A[3][3], double
+ * **coords)`, Listing 2 `burgers(double A[12][12], double **coords,
+ * double **w)`; Table 1 for the objects) takes a zeroed element matrix, the
+ * element's coordinates and its coefficient fields. These entry points apply
+ * that contract to whole meshes on one GPU.
+ *
+ * Conventions shared by every entry point:
+ *  - Reference cells: triangle (0,0),(1,0),(0,1); tetrahedron 0,e1,e2,e3.
+ *  - Geometry: J has columns x_i - x_0, K = J^{-1} (row-major, so that
+ *    d phi/d x_i = sum_a K[a][i] d phi/d X_a, as in Listing 1), integrals use
+ *    |det J|. Geometry is always computed in FP64.
+ *  - Quadrature of degree q: collapsed Gauss-Jacobi product rule with
+ *    m = ceil((q+1)/2) points per direction (m^2 on triangles, m^3 on
+ *    tetrahedra), first direction outermost. quad_degree < 0 selects 2p
+ *    (Burgers: 2p+1).
+ *  - Lagrange P_p dof order: vertices; edges (triangle (1,2),(0,2),(0,1);
+ *    tetrahedron (2,3),(1,3),(1,2),(0,3),(0,2),(0,1)), points from the lower
+ *    to the higher vertex; faces (face f opposite vertex f, lattice points
+ *    (i,j) with j outermost); interior.
+ *  - Vector spaces are component-blocked: local dof (c, a) has index
+ *    c * n_scalar + a. Element matrices are row-major [row = test][col =
+ *    trial], stored cell-major: out[e][i][j].
+ *  - All device pointers are caller-owned; the library allocates nothing per
+ *    call (it keeps one lazily built table cache per device, freed by
+ *    coffee_shutdown). Calls are asynchronous on `hip_stream` (a hipStream_t,
+ *    NULL for the default stream). Host-side validation happens before any
+ *    HIP call and returns a status; faults inside a kernel surface at the
+ *    caller's next synchronisation.
+ *  - Degenerate cells (det J = 0, non-finite input) are not checked on the
+ *    hot path: they yield non-finite output. coffee_check_geometry is the
+ *    explicit check.
+ */
+#ifndef COFFEE_H
+#define COFFEE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    COFFEE_OK = 0,
+    COFFEE_E_INVALID_ARG = 1,      /* null pointer, bad enum, inconsistent sizes */
+    COFFEE_E_UNSUPPORTED = 2,      /* valid request outside the compiled set */
+    COFFEE_E_BUFFER_TOO_SMALL = 3,
+    COFFEE_E_DEGENERATE_CELL = 4,  /* reported by coffee_check_geometry */
+    COFFEE_E_HIP = 5,              /* a HIP runtime call or kernel launch failed */
+    COFFEE_E_NOMEM = 6
+} coffee_status;
+
+typedef enum { COFFEE_TRIANGLE = 2, COFFEE_TETRAHEDRON = 3 } coffee_cell; /* value = dimension */
+
+typedef enum {
+    COFFEE_MASS = 0,         /* int f u v                          fields: [f] or none (f = 1)     */
+    COFFEE_HELMHOLTZ = 1,    /* int grad u . grad v + f u v        fields: [f] or none             */
+    COFFEE_ELASTICITY = 2,   /* int 2 mu eps(u):eps(v) + lambda div u div v (vector)
+                                fields: [mu, lambda] (same degree) or none with constants (mu, lambda) */
+    COFFEE_BURGERS = 3,      /* Jacobian of backward-Euler viscous Burgers at state w (vector):
+                                int (1/dt) du.v + ((w.grad)du).v + ((du.grad)w).v + nu grad du:grad v
+                                fields: [w] (ncomp = d); constants (nu, 1/dt), default (1, 1)   */
+    COFFEE_SVK_ENERGY = 4,   /* St Venant-Kirchhoff: int psi(F), F = I + grad u (one value per cell) */
+    COFFEE_SVK_RESIDUAL = 5, /* int P(F) : grad v, P = F S (vector of N per cell)                  */
+    COFFEE_SVK_JACOBIAN = 6  /* int dP[du] : grad v (N x N per cell)
+                                SVK fields: [u] (ncomp = d); constants (mu, lambda), default (1, 1) */
+} coffee_form;
+
+typedef enum {
+    COFFEE_FP64 = 0,   /* FP64 everywhere, FP64 output                                          */
+    COFFEE_FP32 = 1,   /* FP64 geometry, FP32 contraction, FP32 output                         */
+    COFFEE_BF16X3 = 2  /* FP64 geometry; each contraction operand x split as x_hi = bf16(x),
+                          x_lo = bf16(x - x_hi); hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32
+                          accumulation; FP32 output                                             */
+} coffee_precision;
+
+/* A coefficient field on the cells (device pointers).
+ * cell_to_dof != NULL: values is global [ndofs][ncomp], cell_to_dof is
+ *   [ncells][nloc] int32 with nloc the Lagrange dof count of `degree`.
+ * cell_to_dof == NULL: values is cell-major [ncells][nloc][ncomp].
+ * degree 1..4 (P_p Lagrange). */
+typedef struct {
+    const double* values;
+    const int32_t* cell_to_dof;
+    int32_t degree;
+    int32_t ncomp;
+} coffee_field;
+
+/* Reference quadrature and Lagrange basis tables (host, FP64; paper section 2,
+ * "definition of basis functions": the static const tables W, X, Y of
+ * Listings 1-2 and Table 1). Buffers are caller-owned host memory; pass NULL
+ * for all four to query *nq and *ndof. Layouts: points [nq][d], weights [nq],
+ * basis [nq][ndof], dbasis [d][nq][ndof] (reference derivatives).
+ * Errors: COFFEE_E_INVALID_ARG (bad cell, degree outside 0..4, quad_degree
+ * outside 0..10, null nq/ndof). */
+coffee_status coffee_tabulate(int cell, int degree, int quad_degree, int* nq, int* ndof,
+                              double* points, double* weights, double* basis, double* dbasis);
+
+/* Rows N of the element tensor of (form, cell, degree): n_scalar for scalar
+ * forms, d * n_scalar for vector forms, 0 for the energy, -1 if invalid. */
+int coffee_tensor_dim(int form, int cell, int degree);
+
+/* Element tensors of all cells (paper section 2: "local assembly ... applied
+ * to all cells in the discretized domain"; Fig. 1 contract batched over the
+ * mesh). Inputs (device): coords [nvert][d] FP64, cell_to_vertex [ncells][d+1]
+ * int32, coefficient fields as described above, constants (host) per form.
+ * Output (device, overwritten; equals "zero-initialise then +=" of Fig. 1):
+ * [ncells][N][N] for bilinear forms, [ncells][N] for the residual, [ncells]
+ * for the energy; FP64 if precision == COFFEE_FP64, else FP32.
+ * Errors: COFFEE_E_INVALID_ARG (null pointers, bad enums, negative sizes,
+ * field shape/count not matching the form), COFFEE_E_UNSUPPORTED (degree or
+ * field degree outside the compiled set, precision not available for the
+ * form), COFFEE_E_HIP (launch failure), COFFEE_E_NOMEM (table upload). */
+coffee_status coffee_assemble(int form, int cell, int degree, int quad_degree, int precision,
+                              const double* coords, int64_t nvert, const int32_t* cell_to_vertex,
+                              int64_t ncells, const coffee_field* coeffs, int ncoeff,
+                              const double* constants, int nconst, void* out, void* hip_stream);
+
+/* Reverse mode of the assembly (FP64). With S = sum_e lam_e^T A_e u_e
+ * (bilinear forms), sum_e lam_e^T b_e (residual) or sum_e Pi_e (energy),
+ * accumulates (+=) seed * dS/dcoords into grad_coords [nvert][d] and
+ * seed * dS/dvalues into grad_coeff_values[i] (shaped like coeffs[i].values;
+ * NULL entries or a NULL array skip). lam, u: device [ncells][N] FP64 (lam
+ * unused for the energy, u unused for residual and energy). If cell_value is
+ * not NULL it receives S_e per cell [ncells] FP64 (unscaled).
+ * deterministic = 0: FP64 atomics; 1: per-cell gradients are written to
+ * `workspace` and summed per vertex / dof in a fixed order (bitwise
+ * reproducible). workspace: device buffer of at least
+ * coffee_adjoint_workspace_size(...) bytes (may be NULL if deterministic = 0).
+ * Not a paper passage: the adjoint serves PDE-constrained optimisation and
+ * shape derivatives of the assembled forms.
+ * Errors as coffee_assemble, plus COFFEE_E_BUFFER_TOO_SMALL. */
+coffee_status coffee_assemble_adjoint(int form, int cell, int degree, int quad_degree,
+                                      const double* coords, int64_t nvert, const int32_t* cell_to_vertex,
+                                      int64_t ncells, const coffee_field* coeffs, int ncoeff,
+                                      const double* constants, int nconst,
+                                      const double* lam, const double* u, double seed,
+                                      double* grad_coords, double* const* grad_coeff_values,
+                                      double* cell_value, int deterministic,
+                                      void* workspace, int64_t workspace_bytes, void* hip_stream);
+
+/* Workspace bytes needed by the deterministic adjoint. */
+int64_t coffee_adjoint_workspace_size(int form, int cell, int degree, int64_t nvert, int64_t ncells,
+                                      const coffee_field* coeffs, int ncoeff);
+
+/* Checks every cell: writes to *first_bad (device int64) the smallest cell
+ * index with det J <= 0 or a non-finite coordinate, or -1 if none.
+ * Errors: COFFEE_E_INVALID_ARG. */
+coffee_status coffee_check_geometry(int cell, const double* coords, int64_t nvert,
+                                    const int32_t* cell_to_vertex, int64_t ncells,
+                                    int64_t* first_bad, void* hip_stream);
+
+/* Human-readable name of a status code (static string). */
+const char* coffee_status_string(int status);
+
+/* Launch-shape options for subsequent calls in this process (used by the
+ * autotuner and the benchmark): grid_mult scales the persistent grid (workgroups
+ * = CUs x resident workgroups per CU x grid_mult; 0 restores the default of 1);
+ * nontemporal != 0 issues the element-tensor stores with the streaming
+ * (non-temporal) hint. Not thread-safe with concurrent assembly calls. */
+void coffee_set_launch_options(int grid_mult, int nontemporal);
+
+/* Frees every per-device table cache. Safe to call more than once. */
+void coffee_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,215 @@
+"""Thin Python binding of libcoffee (include/coffee.h): argument marshalling only.
+
+Every function here forwards to the C ABI of the same name; all arithmetic
+runs in the HIP kernels of libcoffee.so. PyTorch provides device memory and
+the current stream. The library must be built (see build.py): importing this
+module without it raises ImportError, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_SO = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcoffee.so")
+
+FORMS = {"mass": 0, "helmholtz": 1, "elasticity": 2, "burgers": 3,
+         "svk_energy": 4, "svk_residual": 5, "svk_jacobian": 6}
+CELLS = {"triangle": 2, "tetrahedron": 3, 2: 2, 3: 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+class CoffeeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {status_string(code)} (status {code})")
+        self.code = code
+
+
+class _Field(C.Structure):
+    _fields_ = [("values", C.c_void_p), ("cell_to_dof", C.c_void_p),
+                ("degree", C.c_int32), ("ncomp", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(_SO):
+        raise ImportError(f"{_SO} is not built: run paper_1407_0904_amd.build.build() first")
+    L = C.CDLL(_SO)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    L.coffee_tabulate.argtypes = [i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_int), vp, vp, vp, vp]
+    L.coffee_tabulate.restype = i32
+    L.coffee_tensor_dim.argtypes = [i32, i32, i32]
+    L.coffee_tensor_dim.restype = i32
+    L.coffee_assemble.argtypes = [i32, i32, i32, i32, i32, vp, i64, vp, i64, vp, i32, vp, i32, vp, vp]
+    L.coffee_assemble.restype = i32
+    L.coffee_assemble_adjoint.argtypes = [i32, i32, i32, i32, vp, i64, vp, i64, vp, i32, vp, i32,
+                                          vp, vp, dbl, vp, vp, vp, i32, vp, i64, vp]
+    L.coffee_assemble_adjoint.restype = i32
+    L.coffee_adjoint_workspace_size.argtypes = [i32, i32, i32, i64, i64, vp, i32]
+    L.coffee_adjoint_workspace_size.restype = i64
+    L.coffee_check_geometry.argtypes = [i32, vp, i64, vp, i64, vp, vp]
+    L.coffee_check_geometry.restype = i32
+    L.coffee_status_string.argtypes = [i32]
+    L.coffee_status_string.restype = C.c_char_p
+    L.coffee_shutdown.argtypes = []
+    L.coffee_shutdown.restype = None
+    L.coffee_set_launch_options.argtypes = [i32, i32]
+    L.coffee_set_launch_options.restype = None
+    return L
+
+
+_lib = _load()
+LIBRARY_PATH = _SO
+
+
+def status_string(code: int) -> str:
+    return _lib.coffee_status_string(int(code)).decode()
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise CoffeeError(code, where)
+
+
+def _dptr(t, dtype, name, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class DeviceField:
+    """A coefficient field on the device (see coffee_field in coffee.h)."""
+    values: torch.Tensor              # float64, global [ndofs, ncomp] or cell-major [E, nloc, ncomp]
+    cell_to_dof: torch.Tensor | None  # int32 [E, nloc] or None
+    degree: int
+    ncomp: int
+
+    @staticmethod
+    def from_host(f, device="cuda") -> "DeviceField":
+        v = torch.as_tensor(np.ascontiguousarray(f.values, dtype=np.float64), device=device)
+        m = None if f.cell_to_dof is None else torch.as_tensor(
+            np.ascontiguousarray(f.cell_to_dof, dtype=np.int32), device=device)
+        return DeviceField(v, m, int(f.degree), int(f.ncomp))
+
+
+def _fields(coeffs):
+    arr = (_Field * max(1, len(coeffs)))()
+    for i, f in enumerate(coeffs):
+        arr[i] = _Field(_dptr(f.values, torch.float64, f"coeffs[{i}].values"),
+                        _dptr(f.cell_to_dof, torch.int32, f"coeffs[{i}].cell_to_dof", allow_none=True),
+                        int(f.degree), int(f.ncomp))
+    return arr
+
+
+def coffee_tabulate(cell, degree: int, quad_degree: int):
+    """Host FP64 tables: (points [nq, d], weights [nq], basis [nq, n], dbasis [d, nq, n])."""
+    c = CELLS[cell]
+    nq, nd = C.c_int(), C.c_int()
+    _check(_lib.coffee_tabulate(c, degree, quad_degree, C.byref(nq), C.byref(nd), None, None, None, None),
+           "coffee_tabulate")
+    q, n = nq.value, nd.value
+    X = np.zeros((q, c)); W = np.zeros(q); B = np.zeros((q, n)); D = np.zeros((c, q, n))
+    _check(_lib.coffee_tabulate(c, degree, quad_degree, C.byref(nq), C.byref(nd), X.ctypes.data,
+                                W.ctypes.data, B.ctypes.data, D.ctypes.data), "coffee_tabulate")
+    return X, W, B, D
+
+
+def coffee_tensor_dim(form, cell, degree: int) -> int:
+    return _lib.coffee_tensor_dim(FORMS[form], CELLS[cell], degree)
+
+
+def output_shape(form, ncells: int, cell, degree: int):
+    N = coffee_tensor_dim(form, cell, degree)
+    if form == "svk_energy":
+        return (ncells,)
+    if form == "svk_residual":
+        return (ncells, N)
+    return (ncells, N, N)
+
+
+def coffee_assemble(form, cell, degree: int, coords: torch.Tensor, cell_to_vertex: torch.Tensor,
+                    coeffs=(), constants=(), quad_degree: int = -1, precision: str = "fp64",
+                    out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Element tensors of every cell (coffee_assemble)."""
+    c = CELLS[cell]
+    ncells = cell_to_vertex.shape[0]
+    odt = torch.float64 if precision == "fp64" else torch.float32
+    if out is None:
+        out = torch.empty(output_shape(form, ncells, c, degree), dtype=odt, device=coords.device)
+    cst = np.ascontiguousarray(constants, dtype=np.float64)
+    st = _lib.coffee_assemble(FORMS[form], c, degree, quad_degree, PRECISIONS[precision],
+                              _dptr(coords, torch.float64, "coords"), coords.shape[0] if coords.ndim else 0,
+                              _dptr(cell_to_vertex, torch.int32, "cell_to_vertex"), ncells,
+                              _fields(list(coeffs)), len(coeffs),
+                              cst.ctypes.data if cst.size else None, cst.size,
+                              _dptr(out, odt, "out"), _stream(stream))
+    _check(st, "coffee_assemble")
+    return out
+
+
+def coffee_assemble_adjoint(form, cell, degree: int, coords, cell_to_vertex, coeffs=(), constants=(),
+                            lam=None, u=None, seed: float = 1.0, grad_coords=None, grad_coeffs=None,
+                            cell_value=None, deterministic: bool = False, quad_degree: int = -1,
+                            workspace=None, stream=None):
+    """Accumulates seed * dS/d(coords, coefficient values); returns (grad_coords, grad_coeffs)."""
+    c = CELLS[cell]
+    ncells = cell_to_vertex.shape[0]
+    if grad_coords is None:
+        grad_coords = torch.zeros_like(coords)
+    if grad_coeffs is None:
+        grad_coeffs = [torch.zeros_like(f.values) for f in coeffs]
+    gptr = (C.c_void_p * max(1, len(coeffs)))(
+        *[_dptr(g, torch.float64, "grad_coeffs", allow_none=True) for g in grad_coeffs])
+    fa = _fields(list(coeffs))
+    if deterministic and workspace is None:
+        nbytes = _lib.coffee_adjoint_workspace_size(FORMS[form], c, degree, coords.shape[0], ncells, fa,
+                                                    len(coeffs))
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=coords.device)
+    cst = np.ascontiguousarray(constants, dtype=np.float64)
+    st = _lib.coffee_assemble_adjoint(
+        FORMS[form], c, degree, quad_degree,
+        _dptr(coords, torch.float64, "coords"), coords.shape[0],
+        _dptr(cell_to_vertex, torch.int32, "cell_to_vertex"), ncells, fa, len(coeffs),
+        cst.ctypes.data if cst.size else None, cst.size,
+        _dptr(lam, torch.float64, "lam", allow_none=True), _dptr(u, torch.float64, "u", allow_none=True),
+        float(seed), _dptr(grad_coords, torch.float64, "grad_coords"), gptr,
+        _dptr(cell_value, torch.float64, "cell_value", allow_none=True), int(bool(deterministic)),
+        None if workspace is None else workspace.data_ptr(), 0 if workspace is None else workspace.numel(),
+        _stream(stream))
+    _check(st, "coffee_assemble_adjoint")
+    return grad_coords, grad_coeffs
+
+
+def coffee_check_geometry(cell, coords, cell_to_vertex, stream=None) -> int:
+    """Smallest bad cell index (det J <= 0 or non-finite), or -1."""
+    fb = torch.empty(1, dtype=torch.int64, device=coords.device)
+    st = _lib.coffee_check_geometry(CELLS[cell], _dptr(coords, torch.float64, "coords"), coords.shape[0],
+                                    _dptr(cell_to_vertex, torch.int32, "cell_to_vertex"),
+                                    cell_to_vertex.shape[0], fb.data_ptr(), _stream(stream))
+    _check(st, "coffee_check_geometry")
+    return int(fb.item())
+
+
+def coffee_set_launch_options(grid_mult: int = 0, nontemporal: int = 0):
+    _lib.coffee_set_launch_options(int(grid_mult), int(nontemporal))
+
+
+def coffee_shutdown():
+    _lib.coffee_shutdown()

@@ -1,0 +1,23 @@
+// Internal declarations shared by the host parts of libcoffee.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/coffee.h"
+
+namespace coffee {
+
+coffee_status validate_common(int form, int cell, int degree, int quad_degree, const double* coords,
+                              int64_t nvert, const int32_t* c2v, int64_t ncells, const coffee_field* coeffs,
+                              int ncoeff, const double* constants, int nconst, int* q_out, int* fd_out);
+
+coffee_status assemble_svk(int form, int cell, int degree, int q, int precision, const double* coords,
+                           int64_t nvert, const int32_t* c2v, int64_t ncells, const coffee_field* coeffs,
+                           const double* constants, int nconst, void* out, void* hip_stream);
+
+int grid_for(int dev, const void* kernel, int64_t nchunks);
+int num_cu(int dev);
+int blocks_per_cu(int dev, const void* kernel);
+
+}  // namespace coffee

@@ -1,0 +1,379 @@
+// libcoffee host library: argument validation, per-device table cache, kernel
+// dispatch and the small utility kernels. The C ABI is declared in
+// include/coffee.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "library.h"
+#include "registry.h"
+#include "tables.h"
+
+namespace coffee {
+
+// ---------------------------------------------------------------- registry
+
+static std::vector<LinEntry>& lin_registry() {
+    static std::vector<LinEntry> reg;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        register_mass_tri(reg);
+        register_mass_tet(reg);
+        register_helmholtz_tri(reg);
+        register_helmholtz_tet(reg);
+        register_elasticity(reg);
+        register_burgers(reg);
+    });
+    return reg;
+}
+
+const LinEntry* find_linear(int form, int dim, int p, int fd, int prec) {
+    for (const LinEntry& e : lin_registry())
+        if (e.form == form && e.dim == dim && e.p == p && e.fd == fd && e.prec == prec) return &e;
+    return nullptr;
+}
+
+// ---------------------------------------------------------------- device table cache
+
+struct DevTable {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct DeviceCtx {
+    std::map<std::tuple<int, int, int, int, int, int>, DevTable> rtab;  // (form, dim, p, q, fd, prec)
+    std::map<const void*, int> occupancy;                               // kernel -> blocks per CU
+    int num_cu = 0;
+};
+
+static std::mutex g_mu;
+static std::map<int, DeviceCtx> g_ctx;
+
+static DeviceCtx& device_ctx(int dev) {
+    DeviceCtx& c = g_ctx[dev];
+    if (c.num_cu == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        c.num_cu = n;
+    }
+    return c;
+}
+
+static uint16_t bf16_bits_host(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+static float bf16_float_host(uint16_t h) {
+    uint32_t u = ((uint32_t)h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Pack reference tensors in MFMA B-fragment order: fragment (t, s) for lane l
+// holds rows k of the K dimension and column ab = 16 t + l % 16.
+static std::vector<char> pack_fragments(const RefTensor& R, int prec) {
+    const int NN = R.NS * R.NS, KR = R.KR;
+    const int NT = (NN + 15) / 16;
+    std::vector<char> buf;
+    if (prec == COFFEE_FP64 || prec == COFFEE_FP32) {
+        const int KS = (KR + 3) / 4;
+        const size_t elem = prec == COFFEE_FP64 ? 8 : 4;
+        buf.assign((size_t)NT * KS * 64 * elem, 0);
+        for (int t = 0; t < NT; ++t)
+            for (int s = 0; s < KS; ++s)
+                for (int l = 0; l < 64; ++l) {
+                    const int k = 4 * s + l / 16, ab = 16 * t + l % 16;
+                    const long double v = (k < KR && ab < NN) ? R.R[(size_t)k * NN + ab] : 0.0L;
+                    const size_t idx = ((size_t)(t * KS + s) * 64 + l);
+                    if (prec == COFFEE_FP64) {
+                        double d = (double)v;
+                        std::memcpy(&buf[idx * 8], &d, 8);
+                    } else {
+                        float f = (float)v;
+                        std::memcpy(&buf[idx * 4], &f, 4);
+                    }
+                }
+    } else {
+        const int KE = 3 * KR, KS = (KE + 31) / 32;
+        buf.assign((size_t)NT * KS * 64 * 16, 0);
+        for (int t = 0; t < NT; ++t)
+            for (int s = 0; s < KS; ++s)
+                for (int l = 0; l < 64; ++l)
+                    for (int jj = 0; jj < 8; ++jj) {
+                        const int kp = 32 * s + 8 * (l / 16) + jj, ab = 16 * t + l % 16;
+                        uint16_t h = 0;
+                        if (kp < KE && ab < NN) {
+                            const int k = kp % KR, part = kp / KR;  // 0: R_hi, 1: R_lo, 2: R_hi
+                            const float x = (float)R.R[(size_t)k * NN + ab];
+                            const uint16_t hi = bf16_bits_host(x);
+                            h = part == 1 ? bf16_bits_host(x - bf16_float_host(hi)) : hi;
+                        }
+                        const size_t idx = (((size_t)(t * KS + s) * 64 + l) * 8 + jj) * 2;
+                        std::memcpy(&buf[idx], &h, 2);
+                    }
+    }
+    return buf;
+}
+
+// Reference fragments for a key, built and uploaded on first use.
+static coffee_status get_rtable(int dev, int form, int dim, int p, int q, int fd, int prec, const void** out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCtx& c = device_ctx(dev);
+    auto key = std::make_tuple(form, dim, p, q, fd, prec);
+    auto it = c.rtab.find(key);
+    if (it != c.rtab.end()) {
+        *out = it->second.ptr;
+        return COFFEE_OK;
+    }
+    RefTensor R;
+    if (!build_reference(form, dim, p, q, fd, R)) return COFFEE_E_INVALID_ARG;
+    std::vector<char> buf = pack_fragments(R, prec);
+    DevTable t;
+    t.bytes = buf.size();
+    if (hipMalloc(&t.ptr, t.bytes) != hipSuccess) return COFFEE_E_NOMEM;
+    if (hipMemcpy(t.ptr, buf.data(), t.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(t.ptr);
+        return COFFEE_E_HIP;
+    }
+    c.rtab[key] = t;
+    *out = t.ptr;
+    return COFFEE_OK;
+}
+
+int blocks_per_cu(int dev, const void* kernel) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCtx& c = device_ctx(dev);
+    auto it = c.occupancy.find(kernel);
+    if (it != c.occupancy.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+    c.occupancy[kernel] = nb;
+    return nb;
+}
+
+int num_cu(int dev) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return device_ctx(dev).num_cu;
+}
+
+// Launch shape override used by the autotuner: grid = cu * blocks_per_cu * mult
+// rounded to a multiple of 8 (XCD count); mult <= 0 selects the default.
+static int t_grid_mult = 0;
+static int t_nontemporal = 0;
+
+int grid_for(int dev, const void* kernel, int64_t nchunks) {
+    const int cus = num_cu(dev);
+    const int nb = blocks_per_cu(dev, kernel);
+    int64_t g = (int64_t)cus * nb * (t_grid_mult > 0 ? t_grid_mult : 1);
+    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    if (g > nchunks) g = nchunks;
+    return (int)std::max<int64_t>(1, g);
+}
+
+}  // namespace coffee
+
+using namespace coffee;
+
+extern "C" void coffee_set_launch_options(int grid_mult, int nontemporal) {
+    t_grid_mult = grid_mult;
+    t_nontemporal = nontemporal;
+}
+
+extern "C" const char* coffee_status_string(int s) {
+    switch (s) {
+        case COFFEE_OK: return "ok";
+        case COFFEE_E_INVALID_ARG: return "invalid argument";
+        case COFFEE_E_UNSUPPORTED: return "unsupported (outside the compiled set)";
+        case COFFEE_E_BUFFER_TOO_SMALL: return "buffer too small";
+        case COFFEE_E_DEGENERATE_CELL: return "degenerate cell";
+        case COFFEE_E_HIP: return "HIP runtime error";
+        case COFFEE_E_NOMEM: return "out of device memory";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int coffee_tensor_dim(int form, int cell, int degree) {
+    if ((cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) || degree < 1 || degree > kMaxP) return -1;
+    const int n = n_scalar(cell, degree);
+    switch (form) {
+        case COFFEE_MASS: case COFFEE_HELMHOLTZ: return n;
+        case COFFEE_ELASTICITY: case COFFEE_BURGERS: case COFFEE_SVK_RESIDUAL: case COFFEE_SVK_JACOBIAN:
+            return cell * n;
+        case COFFEE_SVK_ENERGY: return 0;
+        default: return -1;
+    }
+}
+
+// Validation shared by the forward and adjoint entry points.
+coffee_status coffee::validate_common(int form, int cell, int degree, int quad_degree, const double* coords,
+                                      int64_t nvert, const int32_t* c2v, int64_t ncells,
+                                      const coffee_field* coeffs, int ncoeff, const double* constants,
+                                      int nconst, int* q_out, int* fd_out) {
+    if (form < COFFEE_MASS || form > COFFEE_SVK_JACOBIAN) return COFFEE_E_INVALID_ARG;
+    if (cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) return COFFEE_E_INVALID_ARG;
+    if (degree < 1 || degree > kMaxP) return COFFEE_E_INVALID_ARG;
+    if (quad_degree > 10) return COFFEE_E_INVALID_ARG;
+    if (ncells < 0 || nvert < 0 || nvert > INT32_MAX) return COFFEE_E_INVALID_ARG;
+    if (ncells > 0 && (!coords || !c2v)) return COFFEE_E_INVALID_ARG;
+    if (ncoeff < 0 || ncoeff > 2 || (ncoeff > 0 && !coeffs)) return COFFEE_E_INVALID_ARG;
+    if (nconst < 0 || (nconst > 0 && !constants)) return COFFEE_E_INVALID_ARG;
+    const int d = cell;
+    for (int i = 0; i < ncoeff; ++i) {
+        if (!coeffs[i].values && ncells > 0) return COFFEE_E_INVALID_ARG;
+        if (coeffs[i].degree < 1 || coeffs[i].degree > kMaxP) return COFFEE_E_INVALID_ARG;
+    }
+    int fd = 0;
+    switch (form) {
+        case COFFEE_MASS:
+        case COFFEE_HELMHOLTZ:
+            if (ncoeff > 1) return COFFEE_E_INVALID_ARG;
+            if (ncoeff == 1) {
+                if (coeffs[0].ncomp != 1) return COFFEE_E_INVALID_ARG;
+                fd = coeffs[0].degree;
+            }
+            break;
+        case COFFEE_ELASTICITY:
+            if (ncoeff == 0) {
+                if (nconst < 2) return COFFEE_E_INVALID_ARG;
+            } else {
+                if (ncoeff != 2 || coeffs[0].ncomp != 1 || coeffs[1].ncomp != 1) return COFFEE_E_INVALID_ARG;
+                if (coeffs[0].degree != coeffs[1].degree) return COFFEE_E_UNSUPPORTED;
+                fd = coeffs[0].degree;
+            }
+            break;
+        default:  // Burgers and SVK: one vector field
+            if (ncoeff != 1 || coeffs[0].ncomp != d) return COFFEE_E_INVALID_ARG;
+            fd = coeffs[0].degree;
+    }
+    int q = quad_degree >= 0 ? quad_degree : (form == COFFEE_BURGERS ? 2 * degree + 1 : 2 * degree);
+    if (q > 10) return COFFEE_E_UNSUPPORTED;
+    *q_out = q;
+    *fd_out = fd;
+    return COFFEE_OK;
+}
+
+extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int quad_degree, int precision,
+                                         const double* coords, int64_t nvert, const int32_t* c2v,
+                                         int64_t ncells, const coffee_field* coeffs, int ncoeff,
+                                         const double* constants, int nconst, void* out, void* hip_stream) {
+    int q = 0, fd = 0;
+    coffee_status st = validate_common(form, cell, degree, quad_degree, coords, nvert, c2v, ncells, coeffs,
+                                       ncoeff, constants, nconst, &q, &fd);
+    if (st != COFFEE_OK) return st;
+    if (precision < COFFEE_FP64 || precision > COFFEE_BF16X3) return COFFEE_E_INVALID_ARG;
+    if (ncells > 0 && !out) return COFFEE_E_INVALID_ARG;
+    if (form >= COFFEE_SVK_ENERGY)
+        return assemble_svk(form, cell, degree, q, precision, coords, nvert, c2v, ncells, coeffs, constants,
+                            nconst, out, hip_stream);
+    const LinEntry* e = find_linear(form, cell, degree, fd, precision);
+    if (!e) return COFFEE_E_UNSUPPORTED;
+    if (ncells == 0) return COFFEE_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return COFFEE_E_HIP;
+    const void* rf = nullptr;
+    st = get_rtable(dev, form, cell, degree, q, fd, precision, &rf);
+    if (st != COFFEE_OK) return st;
+    dev::LinArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.coords = coords;
+    a.c2v = c2v;
+    a.ncells = ncells;
+    if (ncoeff >= 1) a.f0 = dev::FieldArg{coeffs[0].values, coeffs[0].cell_to_dof};
+    if (ncoeff >= 2) a.f1 = dev::FieldArg{coeffs[1].values, coeffs[1].cell_to_dof};
+    if (form == COFFEE_BURGERS) {
+        a.c0 = nconst > 0 ? constants[0] : 1.0;
+        a.c1 = nconst > 1 ? constants[1] : 1.0;
+    } else if (form == COFFEE_ELASTICITY && ncoeff == 0) {
+        a.c0 = constants[0];
+        a.c1 = constants[1];
+    }
+    a.rfrag = rf;
+    a.out = out;
+    a.nchunks = (ncells + 255) / 256;
+    a.nontemporal = t_nontemporal;
+    const int grid = grid_for(dev, e->kernel, a.nchunks);
+    if (e->launch(a, (hipStream_t)hip_stream, grid) != hipSuccess) return COFFEE_E_HIP;
+    return COFFEE_OK;
+}
+
+// ---------------------------------------------------------------- geometry check
+
+template <int D>
+__global__ void k_check_geometry(const double* coords, const int32_t* c2v, int64_t ncells, int64_t nvert,
+                                 unsigned long long* first_bad) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncells;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double x[D + 1][D];
+        bool bad = false;
+        for (int v = 0; v <= D; ++v) {
+            const int64_t g = c2v[e * (D + 1) + v];
+            if (g < 0 || g >= nvert) { bad = true; break; }
+            for (int i = 0; i < D; ++i) {
+                x[v][i] = coords[g * D + i];
+                if (!isfinite(x[v][i])) bad = true;
+            }
+        }
+        if (!bad) {
+            double J[D][D];
+            for (int i = 0; i < D; ++i)
+                for (int j = 0; j < D; ++j) J[i][j] = x[j + 1][i] - x[0][i];
+            double det;
+            if constexpr (D == 2) det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            else
+                det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            bad = !(det > 0.0) || !isfinite(det);
+        }
+        if (bad) atomicMin(first_bad, (unsigned long long)e);
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+extern "C" coffee_status coffee_check_geometry(int cell, const double* coords, int64_t nvert,
+                                               const int32_t* c2v, int64_t ncells, int64_t* first_bad,
+                                               void* hip_stream) {
+    if (cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) return COFFEE_E_INVALID_ARG;
+    if (!first_bad || ncells < 0 || nvert < 0 || (ncells > 0 && (!coords || !c2v))) return COFFEE_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)hip_stream;
+    // the sentinel ~0 read as int64 is -1 ("no bad cell")
+    unsigned long long* fb = reinterpret_cast<unsigned long long*>(first_bad);
+    hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, s, fb, ~0ull, (int64_t)1);
+    if (ncells > 0) {
+        const int grid = (int)std::min<int64_t>((ncells + 255) / 256, 4096);
+        if (cell == 2)
+            hipLaunchKernelGGL((k_check_geometry<2>), dim3(grid), dim3(256), 0, s, coords, c2v, ncells, nvert, fb);
+        else
+            hipLaunchKernelGGL((k_check_geometry<3>), dim3(grid), dim3(256), 0, s, coords, c2v, ncells, nvert, fb);
+    }
+    return hipGetLastError() == hipSuccess ? COFFEE_OK : COFFEE_E_HIP;
+}
+
+extern "C" void coffee_shutdown(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_ctx) {
+        (void)hipSetDevice(kv.first);
+        for (auto& t : kv.second.rtab) (void)hipFree(t.second.ptr);
+        kv.second.rtab.clear();
+        kv.second.occupancy.clear();
+    }
+    g_ctx.clear();
+    (void)hipSetDevice(cur);
+}

@@ -1,0 +1,411 @@
+// Device engine for linear forms (mass, Helmholtz, elasticity, Burgers Jacobian).
+//
+// Per cell (paper, section 2, Fig. 1): the Jacobian, its determinant and
+// inverse from the vertex coordinates; coefficient dofs; then the element
+// tensor. Here the element tensor of block (c, c') is the contraction
+//     A[e][c n + a][c' n + b] = sum_k G[e][k] R[k][a n + b]
+// of a per-cell geometry tensor G (built in FP64 from K = J^-1, |det J| and the
+// coefficient dofs) with the reference tensors R (tables.h). Over a tile of 16
+// cells this is a 16 x K by K x 16 matrix product, which runs on MFMA:
+//     FP64   v_mfma_f64_16x16x4f64
+//     FP32   v_mfma_f32_16x16x4f32
+//     BF16X3 v_mfma_f32_16x16x32_bf16 on [G_hi | G_hi | G_lo] x [R_hi ; R_lo ; R_hi]
+//
+// Work layout: a workgroup of 4 waves takes 256 consecutive cells per step
+// (64 per wave, one cell per lane for the geometry), writes G rows to LDS,
+// then each wave contracts its 64 cells as 4 MFMA row tiles. The reference
+// tensors are pre-packed on the host in MFMA B-fragment order so that each
+// fragment load is one coalesced 512-byte (or 1 KiB) read.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace coffee {
+namespace dev {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+enum { F_MASS = 0, F_HELM = 1, F_ELAST = 2, F_BURG = 3 };
+
+constexpr int nsc(int d, int p) { return d == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6; }
+constexpr int npair(int d) { return d * (d + 1) / 2; }
+constexpr int nfield(int d, int fd) { return fd > 0 ? nsc(d, fd) : 1; }
+constexpr int ncomp_space(int form, int d) { return (form == F_ELAST || form == F_BURG) ? d : 1; }
+constexpr int kref(int form, int d, int fd) {
+    return form == F_MASS   ? nfield(d, fd)
+         : form == F_HELM   ? npair(d) + nfield(d, fd)
+         : form == F_ELAST  ? nfield(d, fd) * d * d
+                            : 1 + npair(d) + 2 * nfield(d, fd) * d;
+}
+constexpr int kstep(int prec) { return prec == PREC_BF16X3 ? 32 : 4; }
+constexpr int keff(int form, int d, int fd, int prec) { return prec == PREC_BF16X3 ? 3 * kref(form, d, fd) : kref(form, d, fd); }
+constexpr int ksteps(int form, int d, int fd, int prec) { return (keff(form, d, fd, prec) + kstep(prec) - 1) / kstep(prec); }
+constexpr int ntiles(int d, int p) { return (nsc(d, p) * nsc(d, p) + 15) / 16; }
+
+struct FieldArg {
+    const double* values;
+    const int32_t* map;  // NULL: cell-major values
+};
+
+struct LinArgs {
+    const double* coords;
+    const int32_t* c2v;
+    int64_t ncells;
+    FieldArg f0, f1;
+    double c0, c1;          // elasticity (mu, lambda) if no fields; Burgers (nu, 1/dt)
+    const void* rfrag;      // packed reference fragments
+    void* out;
+    int64_t nchunks;        // ceil(ncells / 256)
+    int nontemporal;
+};
+
+// ---------------------------------------------------------------- geometry
+
+template <int D>
+struct Geom {
+    double K[D][D];
+    double adet;
+};
+
+template <int D>
+__device__ inline void load_geometry(const LinArgs& A, int64_t cell, Geom<D>& g) {
+    double x[D + 1][D];
+    const int32_t* cv = A.c2v + cell * (D + 1);
+#pragma unroll
+    for (int v = 0; v <= D; ++v) {
+        const int64_t gv = cv[v];
+#pragma unroll
+        for (int i = 0; i < D; ++i) x[v][i] = A.coords[gv * D + i];
+    }
+    double J[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) J[i][j] = x[j + 1][i] - x[0][i];
+    if constexpr (D == 2) {
+        const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double r = 1.0 / det;
+        g.K[0][0] = J[1][1] * r;
+        g.K[0][1] = -J[0][1] * r;
+        g.K[1][0] = -J[1][0] * r;
+        g.K[1][1] = J[0][0] * r;
+        g.adet = fabs(det);
+    } else {
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        const double r = 1.0 / det;
+        // K = adj(J) / det, adj(J)[i][j] = cofactor(J)[j][i]
+        g.K[0][0] = c00 * r;
+        g.K[1][0] = c01 * r;
+        g.K[2][0] = c02 * r;
+        g.K[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+        g.K[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+        g.K[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+        g.K[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+        g.K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+        g.K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+        g.adet = fabs(det);
+    }
+}
+
+template <int NL, int NCOMP>
+__device__ inline void load_field(const FieldArg& f, int64_t cell, double (&v)[NL * NCOMP]) {
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int64_t base = f.map ? (int64_t)f.map[cell * NL + r] * NCOMP : (cell * NL + r) * NCOMP;
+#pragma unroll
+        for (int c = 0; c < NCOMP; ++c) v[r * NCOMP + c] = f.values[base + c];
+    }
+}
+
+// ---------------------------------------------------------------- G per form
+
+// Cell data needed by the G builders.
+template <int FORM, int D, int FD>
+struct CellData {
+    static constexpr int NF = nfield(D, FD);
+    static constexpr int WC = (FORM == F_BURG) ? D : 1;
+    Geom<D> g;
+    double f0[FD > 0 ? NF * WC : 1];
+    double f1[(FORM == F_ELAST && FD > 0) ? NF : 1];
+};
+
+template <int FORM, int D, int FD>
+__device__ inline void load_cell(const LinArgs& A, int64_t cell, CellData<FORM, D, FD>& cd) {
+    load_geometry<D>(A, cell, cd.g);
+    constexpr int NF = nfield(D, FD);
+    if constexpr (FD > 0) {
+        load_field<NF, CellData<FORM, D, FD>::WC>(A.f0, cell, cd.f0);
+        if constexpr (FORM == F_ELAST) load_field<NF, 1>(A.f1, cell, cd.f1);
+    }
+}
+
+// G[k] of block (c1, c2) in the tensor order of reference.cpp.
+template <int FORM, int D, int FD, int C1, int C2>
+__device__ inline void build_G(const CellData<FORM, D, FD>& cd, const LinArgs& A, double* G) {
+    constexpr int NF = nfield(D, FD);
+    const auto& K = cd.g.K;
+    const double ad = cd.g.adet;
+    int t = 0;
+    if constexpr (FORM == F_HELM || FORM == F_BURG) {
+        const double sc = (FORM == F_BURG) ? ad * A.c0 : ad;  // nu for Burgers
+        if constexpr (FORM == F_BURG) G[t++] = (C1 == C2) ? ad * A.c1 : 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) s += K[a][i] * K[b][i];
+                G[t++] = (C1 == C2) ? sc * s : 0.0;
+            }
+    }
+    if constexpr (FORM == F_MASS || FORM == F_HELM) {
+#pragma unroll
+        for (int r = 0; r < NF; ++r) G[t++] = (FD > 0) ? ad * cd.f0[r] : ad;
+    } else if constexpr (FORM == F_ELAST) {
+#pragma unroll
+        for (int r = 0; r < NF; ++r) {
+            const double mu = (FD > 0) ? cd.f0[r] : A.c0;
+            const double lm = (FD > 0) ? cd.f1[r] : A.c1;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    double kk = 0.0;
+                    if constexpr (C1 == C2) {
+#pragma unroll
+                        for (int i = 0; i < D; ++i) kk += K[a][i] * K[b][i];
+                    }
+                    G[t++] = ad * (mu * (kk + K[a][C2] * K[b][C1]) + lm * K[a][C1] * K[b][C2]);
+                }
+        }
+    } else if constexpr (FORM == F_BURG) {
+        // C(r, a): delta_c1c2 |det J| sum_i w_{r,i} K[a][i]
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) s += cd.f0[r * D + i] * K[a][i];
+                G[t++] = (C1 == C2) ? ad * s : 0.0;
+            }
+        // E(r, a): |det J| w_{r,c1} K[a][c2]
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int a = 0; a < D; ++a) G[t++] = ad * cd.f0[r * D + C1] * K[a][C2];
+    }
+}
+
+// ---------------------------------------------------------------- precision helpers
+
+__device__ inline u16 bf16_bits_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ inline float bf16_to_float(u16 h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <int PREC> struct PrecT;
+template <> struct PrecT<PREC_F64> { typedef double gtype; typedef double otype; typedef double frag; typedef d4 acc; };
+template <> struct PrecT<PREC_F32> { typedef float gtype; typedef float otype; typedef float frag; typedef f4 acc; };
+template <> struct PrecT<PREC_BF16X3> { typedef u16 gtype; typedef float otype; typedef bf8 frag; typedef f4 acc; };
+
+template <int PREC>
+__device__ inline typename PrecT<PREC>::acc mfma(typename PrecT<PREC>::frag a, typename PrecT<PREC>::frag b,
+                                                 typename PrecT<PREC>::acc c) {
+    if constexpr (PREC == PREC_F64) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else if constexpr (PREC == PREC_F32) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Row (within the 16-row tile) of accumulator element v held by `lane`.
+// Measured on gfx950: FP64 16x16x4 holds rows lane/16 + 4 v; the FP32 and
+// BF16 variants hold rows 4 (lane/16) + v. Columns are lane % 16 for all.
+template <int PREC>
+__device__ inline int acc_row(int lane, int v) {
+    return PREC == PREC_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+}
+
+template <int FORM, int D, int FD, int PREC>
+struct GLayout {
+    static constexpr int KR = kref(FORM, D, FD);
+    static constexpr int KS = ksteps(FORM, D, FD, PREC);
+    // row length in elements: odd (FP64/FP32) so that the 16 rows of a
+    // fragment hit different banks; BF16 rows stay 16-byte aligned and are
+    // shifted by 16 bytes.
+    static constexpr int ROW = PREC == PREC_BF16X3 ? KS * 32 + 8 : KS * 4 + 1;
+};
+
+// Write one cell's G row to LDS (with the hi/lo split for BF16X3).
+template <int FORM, int D, int FD, int PREC>
+__device__ inline void put_G_row(typename PrecT<PREC>::gtype* row, const double* G) {
+    constexpr int KR = kref(FORM, D, FD);
+    constexpr int KS = ksteps(FORM, D, FD, PREC);
+    if constexpr (PREC == PREC_F64) {
+#pragma unroll
+        for (int k = 0; k < KS * 4; ++k) row[k] = k < KR ? G[k < KR ? k : 0] : 0.0;
+    } else if constexpr (PREC == PREC_F32) {
+#pragma unroll
+        for (int k = 0; k < KS * 4; ++k) row[k] = k < KR ? (float)G[k < KR ? k : 0] : 0.0f;
+    } else {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const float x = (float)G[k];
+            const u16 hi = bf16_bits_rne(x);
+            const u16 lo = bf16_bits_rne(x - bf16_to_float(hi));
+            row[k] = hi;
+            row[KR + k] = hi;
+            row[2 * KR + k] = lo;
+        }
+#pragma unroll
+        for (int k = 3 * KR; k < KS * 32; ++k) row[k] = 0;
+    }
+}
+
+template <int PREC>
+__device__ inline typename PrecT<PREC>::frag load_afrag(const typename PrecT<PREC>::gtype* tile, int row_len,
+                                                        int lane, int s) {
+    const int r = lane & 15, g = lane >> 4;
+    if constexpr (PREC == PREC_BF16X3) {
+        return *reinterpret_cast<const bf8*>(tile + r * row_len + 32 * s + 8 * g);
+    } else {
+        return tile[r * row_len + 4 * s + g];
+    }
+}
+
+template <int PREC>
+__device__ inline void store_out(typename PrecT<PREC>::otype* p, typename PrecT<PREC>::otype v, int nt) {
+    if (nt) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Contract one block of the wave's 64 cells and store it.
+template <int FORM, int D, int P, int FD, int PREC, int C1, int C2>
+__device__ inline void contract_block(const LinArgs& A, const typename PrecT<PREC>::gtype* wtile,
+                                      int64_t wave_base, int lane) {
+    using frag_t = typename PrecT<PREC>::frag;
+    using acc_t = typename PrecT<PREC>::acc;
+    using out_t = typename PrecT<PREC>::otype;
+    constexpr int NS = nsc(D, P);
+    constexpr int NN = NS * NS;
+    constexpr int NC = ncomp_space(FORM, D);
+    constexpr int N = NC * NS;
+    constexpr int KS = ksteps(FORM, D, FD, PREC);
+    constexpr int NT = ntiles(D, P);
+    constexpr int ROW = GLayout<FORM, D, FD, PREC>::ROW;
+    constexpr int REGB = NT * KS * (PREC == PREC_F64 ? 2 : (PREC == PREC_F32 ? 1 : 4));
+    constexpr bool RREG = REGB <= 96;
+    constexpr int NTC = NT < 8 ? NT : 8;  // n-tiles held in accumulators at once
+    const frag_t* rf = reinterpret_cast<const frag_t*>(A.rfrag);
+    out_t* out = reinterpret_cast<out_t*>(A.out);
+    const int col = lane & 15;
+
+    frag_t rreg[RREG ? NT : 1][RREG ? KS : 1];
+    if constexpr (RREG) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) rreg[t][s] = rf[(t * KS + s) * 64 + lane];
+    }
+
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        const typename PrecT<PREC>::gtype* tile = wtile + j * 16 * ROW;
+#pragma unroll 1
+        for (int t0 = 0; t0 < NT; t0 += NTC) {
+            acc_t acc[NTC];
+#pragma unroll
+            for (int t = 0; t < NTC; ++t) acc[t] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const frag_t a = load_afrag<PREC>(tile, ROW, lane, s);
+#pragma unroll
+                for (int t = 0; t < NTC; ++t) {
+                    if (t0 + t < NT) {
+                        frag_t b;
+                        if constexpr (RREG) b = rreg[t0 + t < NT ? t0 + t : 0][s];
+                        else b = rf[((t0 + t) * KS + s) * 64 + lane];
+                        acc[t] = mfma<PREC>(a, b, acc[t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NTC; ++t) {
+                const int ab = (t0 + t) * 16 + col;
+                if (t0 + t >= NT || ab >= NN) continue;
+                const int a = ab / NS, b = ab - (ab / NS) * NS;
+                const int64_t off_in_cell = (int64_t)(C1 * NS + a) * N + C2 * NS + b;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t cell = wave_base + j * 16 + acc_row<PREC>(lane, v);
+                    if (cell < A.ncells)
+                        store_out<PREC>(out + cell * (int64_t)N * N + off_in_cell, (out_t)acc[t][v], A.nontemporal);
+                }
+            }
+        }
+    }
+}
+
+template <int FORM, int D, int P, int FD, int PREC, int B>
+__device__ inline void do_block(const LinArgs& A, const CellData<FORM, D, FD>& cd, bool valid,
+                                typename PrecT<PREC>::gtype* wtile, int64_t wave_base, int lane) {
+    constexpr int NC = ncomp_space(FORM, D);
+    constexpr int C1 = B / NC, C2 = B % NC;
+    constexpr int KR = kref(FORM, D, FD);
+    constexpr int ROW = GLayout<FORM, D, FD, PREC>::ROW;
+    double G[KR];
+    if (valid) build_G<FORM, D, FD, C1, C2>(cd, A, G);
+    else {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) G[k] = 0.0;
+    }
+    put_G_row<FORM, D, FD, PREC>(wtile + lane * ROW, G);
+    __syncthreads();
+    contract_block<FORM, D, P, FD, PREC, C1, C2>(A, wtile, wave_base, lane);
+    __syncthreads();
+}
+
+template <int FORM, int D, int P, int FD, int PREC, int B, int NB>
+__device__ inline void do_blocks(const LinArgs& A, const CellData<FORM, D, FD>& cd, bool valid,
+                                 typename PrecT<PREC>::gtype* wtile, int64_t wave_base, int lane) {
+    if constexpr (B < NB) {
+        do_block<FORM, D, P, FD, PREC, B>(A, cd, valid, wtile, wave_base, lane);
+        do_blocks<FORM, D, P, FD, PREC, B + 1, NB>(A, cd, valid, wtile, wave_base, lane);
+    }
+}
+
+template <int FORM, int D, int P, int FD, int PREC>
+__global__ __launch_bounds__(256) void k_linear(LinArgs A) {
+    using g_t = typename PrecT<PREC>::gtype;
+    constexpr int ROW = GLayout<FORM, D, FD, PREC>::ROW;
+    constexpr int NC = ncomp_space(FORM, D);
+    __shared__ __attribute__((aligned(16))) g_t sG[4 * 64 * ROW];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    g_t* wtile = sG + wave * 64 * ROW;
+    // XCD-aware order: consecutive logical workgroups of one XCD (round-robin
+    // dispatch, 8 XCDs) take consecutive chunks of cells.
+    const int64_t G = gridDim.x;
+    const int64_t b = blockIdx.x;
+    const int64_t logical = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    for (int64_t chunk = logical; chunk < A.nchunks; chunk += G) {
+        const int64_t wave_base = chunk * 256 + wave * 64;
+        const int64_t cell = wave_base + lane;
+        const bool valid = cell < A.ncells;
+        CellData<FORM, D, FD> cd;
+        if (valid) load_cell<FORM, D, FD>(A, cell, cd);
+        do_blocks<FORM, D, P, FD, PREC, 0, NC * NC>(A, cd, valid, wtile, wave_base, lane);
+    }
+}
+
+}  // namespace dev
+}  // namespace coffee

@@ -1,0 +1,47 @@
+// Kernel registry of libcoffee (internal header): every compiled (form, cell,
+// degree, field degree, precision) instance of the device engines.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "linear.hpp"
+
+namespace coffee {
+
+typedef hipError_t (*LinLaunch)(const dev::LinArgs&, hipStream_t, int grid);
+
+struct LinEntry {
+    int form, dim, p, fd, prec;
+    LinLaunch launch;
+    const void* kernel;
+};
+
+template <int FORM, int D, int P, int FD, int PREC>
+hipError_t launch_linear(const dev::LinArgs& a, hipStream_t s, int grid) {
+    hipLaunchKernelGGL((dev::k_linear<FORM, D, P, FD, PREC>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int FORM, int D, int P, int FD, int PREC>
+LinEntry lin_entry() {
+    return LinEntry{FORM, D, P, FD, PREC, &launch_linear<FORM, D, P, FD, PREC>,
+                    reinterpret_cast<const void*>(&dev::k_linear<FORM, D, P, FD, PREC>)};
+}
+
+// one instance for each precision
+template <int FORM, int D, int P, int FD>
+void add_all_prec(std::vector<LinEntry>& v) {
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F64>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F32>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_BF16X3>());
+}
+
+void register_mass_tri(std::vector<LinEntry>& v);
+void register_mass_tet(std::vector<LinEntry>& v);
+void register_helmholtz_tri(std::vector<LinEntry>& v);
+void register_helmholtz_tet(std::vector<LinEntry>& v);
+void register_elasticity(std::vector<LinEntry>& v);
+void register_burgers(std::vector<LinEntry>& v);
+
+}  // namespace coffee

@@ -1,0 +1,91 @@
+"""C ABI of libcoffee without a GPU: exported symbols, host validation and the
+host tabulation (checked against the oracle's independent tables)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SO = os.path.join(ROOT, "paper_1407_0904_amd", "libcoffee.so")
+HDR = os.path.join(ROOT, "include", "coffee.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(SO):
+        from paper_1407_0904_amd import build
+        build.build()
+    return C.CDLL(SO)
+
+
+def declared_functions():
+    text = open(HDR).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(coffee_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "coffee_assemble" in names and "coffee_tabulate" in names and "coffee_assemble_adjoint" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    lib.coffee_status_string.restype = C.c_char_p
+    assert lib.coffee_status_string(0) == b"ok"
+    assert b"invalid" in lib.coffee_status_string(1)
+    assert lib.coffee_status_string(99) == b"unknown status"
+
+
+def _assemble(lib, form=1, cell=2, degree=1, q=-1, prec=0, coords=None, nvert=3, c2v=None, ncells=1,
+              coeffs=None, ncoeff=0, consts=None, nconst=0, out=None):
+    f = lib.coffee_assemble
+    f.argtypes = [C.c_int] * 5 + [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
+                                  C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+    return f(form, cell, degree, q, prec, coords, nvert, c2v, ncells, coeffs, ncoeff, consts, nconst, out, None)
+
+
+def test_validation_before_any_hip_call(lib):
+    """Invalid arguments are rejected on the host (status 1/2), never reaching HIP."""
+    dummy = C.c_void_p(16)  # never dereferenced: validation fails first
+    assert _assemble(lib, coords=None, c2v=dummy, out=dummy) == 1
+    assert _assemble(lib, coords=dummy, c2v=None, out=dummy) == 1
+    assert _assemble(lib, coords=dummy, c2v=dummy, out=None) == 1
+    assert _assemble(lib, form=9, coords=dummy, c2v=dummy, out=dummy) == 1
+    assert _assemble(lib, cell=4, coords=dummy, c2v=dummy, out=dummy) == 1
+    assert _assemble(lib, degree=0, coords=dummy, c2v=dummy, out=dummy) == 1
+    assert _assemble(lib, degree=5, coords=dummy, c2v=dummy, out=dummy) == 1
+    assert _assemble(lib, prec=3, coords=dummy, c2v=dummy, out=dummy) == 1
+    assert _assemble(lib, ncells=-1, coords=dummy, c2v=dummy, out=dummy) == 1
+    assert _assemble(lib, q=11, coords=dummy, c2v=dummy, out=dummy) == 1
+    # elasticity without fields needs (mu, lambda)
+    assert _assemble(lib, form=2, coords=dummy, c2v=dummy, out=dummy) == 1
+    # Burgers needs one vector field
+    assert _assemble(lib, form=3, coords=dummy, c2v=dummy, out=dummy) == 1
+
+
+def test_tensor_dims(lib):
+    f = lib.coffee_tensor_dim
+    assert f(1, 2, 1) == 3 and f(1, 3, 2) == 10 and f(2, 3, 2) == 30 and f(3, 3, 1) == 12
+    assert f(0, 3, 4) == 35 and f(4, 3, 2) == 0 and f(6, 3, 2) == 30 and f(9, 3, 2) == -1
+
+
+@pytest.mark.parametrize("d,p,q", [(2, 1, 2), (2, 4, 8), (3, 2, 4), (3, 3, 6), (3, 4, 8), (2, 2, 5), (3, 0, 3)])
+def test_tabulate_matches_oracle(lib, oracle, d, p, q):
+    """Golub-Welsch + Vandermonde tables equal the oracle's Newton + Silvester tables."""
+    nq, nd = C.c_int(), C.c_int()
+    tab = lib.coffee_tabulate
+    tab.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)] + [C.c_void_p] * 4
+    assert tab(d, p, q, C.byref(nq), C.byref(nd), None, None, None, None) == 0
+    X = np.zeros((nq.value, d)); W = np.zeros(nq.value); B = np.zeros((nq.value, nd.value))
+    D = np.zeros((d, nq.value, nd.value))
+    assert tab(d, p, q, C.byref(nq), C.byref(nd), X.ctypes.data, W.ctypes.data, B.ctypes.data, D.ctypes.data) == 0
+    Xo, Wo, Bo, Do = oracle.tabulate(d, p, q)
+    np.testing.assert_allclose(X, Xo, atol=1e-15)
+    np.testing.assert_allclose(W, Wo, rtol=1e-14)
+    np.testing.assert_allclose(B, Bo, atol=2e-14)
+    np.testing.assert_allclose(D, Do, atol=1e-13)
+    assert tab(5, p, q, C.byref(nq), C.byref(nd), None, None, None, None) == 1

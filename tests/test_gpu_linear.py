@@ -1,0 +1,162 @@
+"""GPU parity of the linear-form engine (mass, Helmholtz, elasticity, Burgers)
+against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_1407_0904_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a device"
+    from paper_1407_0904_amd import coffee
+    return coffee
+
+
+def _field_of_degree(mesh, deg, rng, lo=0.5, hi=1.5, ncomp=1):
+    if deg == 1:
+        return I.Field(rng.uniform(lo, hi, size=(mesh.nvert, ncomp)), mesh.cells, 1, ncomp)
+    if deg == 2:
+        c2d, nd = I.p2_dofmap(mesh.cells, mesh.n, mesh.d)
+        return I.Field(rng.uniform(lo, hi, size=(nd, ncomp)), c2d, 2, ncomp)
+    nl = I.n_scalar_dofs(mesh.d, deg)
+    return I.Field(rng.uniform(lo, hi, size=(mesh.ncells, nl, ncomp)), None, deg, ncomp)
+
+
+PRECS = ["fp64", "fp32", "bf16x3"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_helmholtz_p1_tri_full_config(cf, oracle, prec):
+    """8192-cell Helmholtz P1 triangle workload, every cell."""
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    w = I.workload("helmholtz_p1_tri")
+    ref = oracle.assemble(w.form, w.mesh, w.degree, w.quad_degree, fields=w.fields)
+    got = assemble_gpu(w.form, w.mesh, w.degree, w.fields, quad_degree=w.quad_degree, precision=prec).cpu().numpy()
+    err = cell_rel_err(got, ref)
+    print(f"helmholtz_p1_tri {prec} max cell rel err {err:.3e}")
+    assert err < TOL[prec]
+
+
+CASES = [
+    # form, d, p, field degree (0 = none)
+    ("mass", 2, 1, 0), ("mass", 2, 2, 1), ("mass", 2, 3, 2), ("mass", 2, 4, 1),
+    ("mass", 3, 1, 1), ("mass", 3, 2, 2), ("mass", 3, 3, 1), ("mass", 3, 4, 0),
+    ("helmholtz", 2, 1, 1), ("helmholtz", 2, 2, 2), ("helmholtz", 2, 3, 1), ("helmholtz", 2, 4, 2),
+    ("helmholtz", 3, 1, 0), ("helmholtz", 3, 2, 2), ("helmholtz", 3, 3, 1), ("helmholtz", 3, 4, 1),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("form,d,p,fd", CASES)
+def test_scalar_forms(cf, oracle, form, d, p, fd, prec):
+    """Small meshes spanning several 256-cell chunks with a ragged tail."""
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    rng = np.random.default_rng(100 + 10 * d + p)
+    mesh = I.make_mesh(d, 13 if d == 2 else 5, 0.2 if d == 2 else 0.1, rng)  # 338 / 750 cells
+    fields = [] if fd == 0 else [_field_of_degree(mesh, fd, rng)]
+    ref = oracle.assemble(form, mesh, p, fields=fields)
+    got = assemble_gpu(form, mesh, p, fields, precision=prec).cpu().numpy()
+    err = cell_rel_err(got, ref)
+    print(f"{form} d{d} p{p} fd{fd} {prec}: {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("d,p,fields", [(3, 2, True), (3, 1, True), (3, 2, False), (2, 2, True), (3, 3, True),
+                                        (2, 3, False)])
+def test_elasticity(cf, oracle, d, p, fields, prec):
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    rng = np.random.default_rng(7 + p)
+    mesh = I.make_mesh(d, 10 if d == 2 else 4, 0.1, rng)
+    if fields:
+        flds = [_field_of_degree(mesh, 1, rng, 1, 10), _field_of_degree(mesh, 1, rng, 1, 10)]
+        cst = []
+    else:
+        flds, cst = [], [2.5, 7.0]
+    ref = oracle.assemble("elasticity", mesh, p, fields=flds, constants=cst)
+    got = assemble_gpu("elasticity", mesh, p, flds, constants=cst, precision=prec).cpu().numpy()
+    err = cell_rel_err(got, ref)
+    print(f"elasticity d{d} p{p} {prec}: {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("d,p", [(3, 1), (3, 2), (2, 1), (2, 2), (2, 3)])
+def test_burgers(cf, oracle, d, p, prec):
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    rng = np.random.default_rng(70 + p)
+    mesh = I.make_mesh(d, 10 if d == 2 else 4, 0.1, rng)
+    w = _field_of_degree(mesh, p, rng, -1, 1, ncomp=d)
+    cst = [0.7, 1.3]
+    ref = oracle.assemble("burgers", mesh, p, fields=[w], constants=cst)
+    got = assemble_gpu("burgers", mesh, p, [w], constants=cst, precision=prec).cpu().numpy()
+    err = cell_rel_err(got, ref)
+    print(f"burgers d{d} p{p} {prec}: {err:.3e}")
+    assert err < TOL[prec]
+
+
+def test_edge_cases(cf, oracle):
+    """Empty input, a single cell, exactly one chunk, one chunk + 1, cell-major fields."""
+    import torch
+    from gpu_util import assemble_gpu, cell_rel_err, to_dev
+    rng = np.random.default_rng(5)
+    mesh = I.random_cells(3, 257, rng)
+    f = I.Field(rng.uniform(0.5, 1.5, size=(257, 10, 1)), None, 2, 1)  # cell-major (no map)
+    for ncell in (1, 64, 256, 257):
+        sub = I.Mesh(3, 0, mesh.coords, mesh.cells[:ncell])
+        fs = I.Field(f.values[:ncell], None, 2, 1)
+        ref = oracle.assemble("helmholtz", sub, 3, fields=[fs])
+        got = assemble_gpu("helmholtz", sub, 3, [fs]).cpu().numpy()
+        assert cell_rel_err(got, ref) < 1e-12
+    coords, c2v, _ = to_dev(mesh, [])
+    empty = torch.empty((0, 4), dtype=torch.int32, device=coords.device)
+    out = cf.coffee_assemble("mass", 3, 2, coords, empty)
+    assert out.shape == (0, 10, 10)
+    # a field degree outside the compiled set is reported, not silently run
+    f3 = I.Field(rng.uniform(0.5, 1.5, size=(4, 20, 1)), None, 3, 1)
+    sub = I.Mesh(3, 0, mesh.coords, mesh.cells[:4])
+    with pytest.raises(cf.CoffeeError) as ei:
+        assemble_gpu("helmholtz", sub, 3, [f3])
+    assert ei.value.code == 2
+
+
+def test_full_size_helmholtz_p2_tet_sampled(cf, oracle):
+    """The 1,572,864-cell Helmholtz P2 tetrahedron workload in the benchmark's
+    launch configuration; sampled cells against the oracle, plus the total
+    mass identity on all cells."""
+    import torch
+    from gpu_util import TOL, cell_rel_err, to_dev
+    w = I.workload("helmholtz_p2_tet")
+    coords, c2v, dfs = to_dev(w.mesh, w.fields)
+    rng = np.random.default_rng(11)
+    E = w.mesh.ncells
+    sample = np.unique(np.concatenate([[0, 1, 255, 256, E - 1], rng.integers(0, E, 3000)]))
+    ref = oracle.assemble(w.form, w.mesh, 2, 4, fields=w.fields, cells=sample)
+    idx = torch.as_tensor(sample, device=coords.device)
+    for prec in PRECS:
+        out = cf.coffee_assemble(w.form, 3, 2, coords, c2v, coeffs=dfs, quad_degree=4, precision=prec)
+        torch.cuda.synchronize()
+        got = out[idx].cpu().numpy()
+        err = cell_rel_err(got, ref)
+        print(f"helmholtz_p2_tet full {prec}: {err:.3e}")
+        assert err < TOL[prec]
+        del out
+    # f = 1 mass over the whole mesh sums to the cube's volume
+    m = cf.coffee_assemble("mass", 3, 2, coords, c2v)
+    assert abs(float(m.sum()) - 1.0) < 1e-10
+
+
+def test_check_geometry(cf):
+    import torch
+    from gpu_util import to_dev
+    mesh = I.make_mesh(3, 4, 0.1, np.random.default_rng(0))
+    coords, c2v, _ = to_dev(mesh, [])
+    assert cf.coffee_check_geometry(3, coords, c2v) == -1
+    bad = c2v.clone()
+    bad[37] = bad[37][[0, 2, 1, 3]]  # inverted orientation
+    bad[200, 1] = bad[200, 0]        # collapsed
+    assert cf.coffee_check_geometry(3, coords, bad) == 37
