@@ -109,8 +109,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of the output's byte size (counter calibration)")
     ap.add_argument("--grid-mult", type=int, default=0)
-    ap.add_argument("--nontemporal", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: local assembly needs no communication on the forward path, "
@@ -127,7 +128,7 @@ def main():
     coords = torch.as_tensor(w.mesh.coords, device=dev)
     c2v = torch.as_tensor(w.mesh.cells, device=dev)
     fields = [coffee.DeviceField.from_host(f, dev) for f in w.fields]
-    coffee.coffee_set_launch_options(args.grid_mult, args.nontemporal)
+    coffee.coffee_set_launch_options(args.grid_mult)
 
     def run(prec, out):
         return lambda: coffee.coffee_assemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields,
@@ -153,6 +154,17 @@ def main():
                          "gbs": nbytes / (kms * 1e-3) / 1e9, "bytes": nbytes, "err": err}
         del out
         torch.cuda.synchronize()
+
+    if args.calibrate_copy:
+        # a plain copy kernel of known size, for scaling the HBM byte counters
+        nb = int(np.prod(shape)) * 8
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"calibration copy: {nb} bytes read and {nb} bytes written per launch", file=sys.stderr)
+        del src, dst
 
     main_r = results[args.precision]
     line = {

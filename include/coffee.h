@@ -111,8 +111,11 @@ int coffee_tensor_dim(int form, int cell, int degree);
  * int32, coefficient fields as described above, constants (host) per form.
  * Output (device, overwritten; equals "zero-initialise then +=" of Fig. 1):
  * [ncells][N][N] for bilinear forms, [ncells][N] for the residual, [ncells]
- * for the energy; FP64 if precision == COFFEE_FP64, else FP32.
+ * for the energy; FP64 if precision == COFFEE_FP64, else FP32. `out` must be
+ * 16-byte aligned. cell_to_vertex and cell_to_dof entries must be valid
+ * indices (coffee_check_geometry validates the vertex indices).
  * Errors: COFFEE_E_INVALID_ARG (null pointers, bad enums, negative sizes,
+ * misaligned out,
  * field shape/count not matching the form), COFFEE_E_UNSUPPORTED (degree or
  * field degree outside the compiled set, precision not available for the
  * form), COFFEE_E_HIP (launch failure), COFFEE_E_NOMEM (table upload). */
@@ -158,12 +161,13 @@ coffee_status coffee_check_geometry(int cell, const double* coords, int64_t nver
 /* Human-readable name of a status code (static string). */
 const char* coffee_status_string(int status);
 
-/* Launch-shape options for subsequent calls in this process (used by the
- * autotuner and the benchmark): grid_mult scales the persistent grid (workgroups
- * = CUs x resident workgroups per CU x grid_mult; 0 restores the default of 1);
- * nontemporal != 0 issues the element-tensor stores with the streaming
- * (non-temporal) hint. Not thread-safe with concurrent assembly calls. */
-void coffee_set_launch_options(int grid_mult, int nontemporal);
+/* Launch-shape option for subsequent calls in this process (used by the
+ * autotuner and the benchmark): grid_mult scales the grid (workgroups = CUs x
+ * resident workgroups per CU x grid_mult, capped at one workgroup per 256
+ * cells); 0 restores the defaults: 1 for mass and Helmholtz, whose kernel is
+ * persistent, one workgroup per 256 cells for the other forms. Not
+ * thread-safe with concurrent assembly calls. */
+void coffee_set_launch_options(int grid_mult);
 
 /* Frees every per-device table cache. Safe to call more than once. */
 void coffee_shutdown(void);

@@ -55,7 +55,7 @@ def _load():
     L.coffee_status_string.restype = C.c_char_p
     L.coffee_shutdown.argtypes = []
     L.coffee_shutdown.restype = None
-    L.coffee_set_launch_options.argtypes = [i32, i32]
+    L.coffee_set_launch_options.argtypes = [i32]
     L.coffee_set_launch_options.restype = None
     return L
 
@@ -207,8 +207,8 @@ def coffee_check_geometry(cell, coords, cell_to_vertex, stream=None) -> int:
     return int(fb.item())
 
 
-def coffee_set_launch_options(grid_mult: int = 0, nontemporal: int = 0):
-    _lib.coffee_set_launch_options(int(grid_mult), int(nontemporal))
+def coffee_set_launch_options(grid_mult: int = 0):
+    _lib.coffee_set_launch_options(int(grid_mult))
 
 
 def coffee_shutdown():

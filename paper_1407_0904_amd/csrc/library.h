@@ -16,7 +16,7 @@ coffee_status assemble_svk(int form, int cell, int degree, int q, int precision,
                            int64_t nvert, const int32_t* c2v, int64_t ncells, const coffee_field* coeffs,
                            const double* constants, int nconst, void* out, void* hip_stream);
 
-int grid_for(int dev, const void* kernel, int64_t nchunks);
+int grid_for(int dev, const void* kernel, int64_t nchunks, int default_mult);
 int num_cu(int dev);
 int blocks_per_cu(int dev, const void* kernel);
 

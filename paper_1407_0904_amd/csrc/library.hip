@@ -80,10 +80,20 @@ static float bf16_float_host(uint16_t h) {
 }
 
 // Pack reference tensors in MFMA B-fragment order: fragment (t, s) for lane l
-// holds rows k of the K dimension and column ab = 16 t + l % 16.
-static std::vector<char> pack_fragments(const RefTensor& R, int prec) {
-    const int NN = R.NS * R.NS, KR = R.KR;
-    const int NT = (NN + 15) / 16;
+// holds rows k of the K dimension and output column 16 t + l % 16. Columns are
+// the entries ab = a n + b, or for symmetric forms the entries a <= b of the
+// upper triangle in row-major order.
+static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym) {
+    const int NS = R.NS, NN = R.NS * R.NS, KR = R.KR;
+    std::vector<int> colmap;
+    if (sym) {
+        for (int a = 0; a < NS; ++a)
+            for (int b = a; b < NS; ++b) colmap.push_back(a * NS + b);
+    } else {
+        for (int ab = 0; ab < NN; ++ab) colmap.push_back(ab);
+    }
+    const int NC = (int)colmap.size();
+    const int NT = (NC + 15) / 16;
     std::vector<char> buf;
     if (prec == COFFEE_FP64 || prec == COFFEE_FP32) {
         const int KS = (KR + 3) / 4;
@@ -92,8 +102,8 @@ static std::vector<char> pack_fragments(const RefTensor& R, int prec) {
         for (int t = 0; t < NT; ++t)
             for (int s = 0; s < KS; ++s)
                 for (int l = 0; l < 64; ++l) {
-                    const int k = 4 * s + l / 16, ab = 16 * t + l % 16;
-                    const long double v = (k < KR && ab < NN) ? R.R[(size_t)k * NN + ab] : 0.0L;
+                    const int k = 4 * s + l / 16, c = 16 * t + l % 16;
+                    const long double v = (k < KR && c < NC) ? R.R[(size_t)k * NN + colmap[c]] : 0.0L;
                     const size_t idx = ((size_t)(t * KS + s) * 64 + l);
                     if (prec == COFFEE_FP64) {
                         double d = (double)v;
@@ -110,11 +120,11 @@ static std::vector<char> pack_fragments(const RefTensor& R, int prec) {
             for (int s = 0; s < KS; ++s)
                 for (int l = 0; l < 64; ++l)
                     for (int jj = 0; jj < 8; ++jj) {
-                        const int kp = 32 * s + 8 * (l / 16) + jj, ab = 16 * t + l % 16;
+                        const int kp = 32 * s + 8 * (l / 16) + jj, c = 16 * t + l % 16;
                         uint16_t h = 0;
-                        if (kp < KE && ab < NN) {
+                        if (kp < KE && c < NC) {
                             const int k = kp % KR, part = kp / KR;  // 0: R_hi, 1: R_lo, 2: R_hi
-                            const float x = (float)R.R[(size_t)k * NN + ab];
+                            const float x = (float)R.R[(size_t)k * NN + colmap[c]];
                             const uint16_t hi = bf16_bits_host(x);
                             h = part == 1 ? bf16_bits_host(x - bf16_float_host(hi)) : hi;
                         }
@@ -137,7 +147,7 @@ static coffee_status get_rtable(int dev, int form, int dim, int p, int q, int fd
     }
     RefTensor R;
     if (!build_reference(form, dim, p, q, fd, R)) return COFFEE_E_INVALID_ARG;
-    std::vector<char> buf = pack_fragments(R, prec);
+    std::vector<char> buf = pack_fragments(R, prec, uses_scalar_engine(form));
     DevTable t;
     t.bytes = buf.size();
     if (hipMalloc(&t.ptr, t.bytes) != hipSuccess) return COFFEE_E_NOMEM;
@@ -167,14 +177,15 @@ int num_cu(int dev) {
 }
 
 // Launch shape override used by the autotuner: grid = cu * blocks_per_cu * mult
-// rounded to a multiple of 8 (XCD count); mult <= 0 selects the default.
+// rounded to a multiple of 8 (XCD count); mult <= 0 selects the engine's
+// default: the pipelined symmetric engine is persistent (a few resident waves of
+// workgroups), the block engine takes one workgroup per 256-cell chunk.
 static int t_grid_mult = 0;
-static int t_nontemporal = 0;
 
-int grid_for(int dev, const void* kernel, int64_t nchunks) {
+int grid_for(int dev, const void* kernel, int64_t nchunks, int default_mult) {
     const int cus = num_cu(dev);
     const int nb = blocks_per_cu(dev, kernel);
-    int64_t g = (int64_t)cus * nb * (t_grid_mult > 0 ? t_grid_mult : 1);
+    int64_t g = (int64_t)cus * nb * (t_grid_mult > 0 ? t_grid_mult : default_mult);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     if (g > nchunks) g = nchunks;
     return (int)std::max<int64_t>(1, g);
@@ -184,10 +195,7 @@ int grid_for(int dev, const void* kernel, int64_t nchunks) {
 
 using namespace coffee;
 
-extern "C" void coffee_set_launch_options(int grid_mult, int nontemporal) {
-    t_grid_mult = grid_mult;
-    t_nontemporal = nontemporal;
-}
+extern "C" void coffee_set_launch_options(int grid_mult) { t_grid_mult = grid_mult; }
 
 extern "C" const char* coffee_status_string(int s) {
     switch (s) {
@@ -272,6 +280,7 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     if (st != COFFEE_OK) return st;
     if (precision < COFFEE_FP64 || precision > COFFEE_BF16X3) return COFFEE_E_INVALID_ARG;
     if (ncells > 0 && !out) return COFFEE_E_INVALID_ARG;
+    if (((uintptr_t)out & 15) != 0) return COFFEE_E_INVALID_ARG;
     if (form >= COFFEE_SVK_ENERGY)
         return assemble_svk(form, cell, degree, q, precision, coords, nvert, c2v, ncells, coeffs, constants,
                             nconst, out, hip_stream);
@@ -300,8 +309,7 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     a.rfrag = rf;
     a.out = out;
     a.nchunks = (ncells + 255) / 256;
-    a.nontemporal = t_nontemporal;
-    const int grid = grid_for(dev, e->kernel, a.nchunks);
+    const int grid = grid_for(dev, e->kernel, a.nchunks, uses_scalar_engine(form) ? 1 : 64);
     if (e->launch(a, (hipStream_t)hip_stream, grid) != hipSuccess) return COFFEE_E_HIP;
     return COFFEE_OK;
 }

@@ -61,7 +61,6 @@ struct LinArgs {
     const void* rfrag;      // packed reference fragments
     void* out;
     int64_t nchunks;        // ceil(ncells / 256)
-    int nontemporal;
 };
 
 // ---------------------------------------------------------------- geometry
@@ -72,16 +71,75 @@ struct Geom {
     double adet;
 };
 
-template <int D>
-__device__ inline void load_geometry(const LinArgs& A, int64_t cell, Geom<D>& g) {
+// ---------------------------------------------------------------- split gathers
+// The gathers of one cell in two dependent stages, so that a persistent loop
+// can issue them for a later chunk while the current chunk is contracted.
+
+template <int FORM, int D, int FD>
+struct CellIdx {
+    static constexpr int NF = nfield(D, FD);
+    int v[D + 1];
+    int f0[FD > 0 ? NF : 1];
+    int f1[(FORM == F_ELAST && FD > 0) ? NF : 1];
+};
+
+template <int FORM, int D, int FD>
+struct CellRaw {
+    static constexpr int NF = nfield(D, FD);
+    static constexpr int WC = (FORM == F_BURG) ? D : 1;
     double x[D + 1][D];
+    double f0[FD > 0 ? NF * WC : 1];
+    double f1[(FORM == F_ELAST && FD > 0) ? NF : 1];
+};
+
+template <int FORM, int D, int FD>
+__device__ inline void load_idx(const LinArgs& A, int64_t cell, CellIdx<FORM, D, FD>& ix) {
+    constexpr int NF = nfield(D, FD);
     const int32_t* cv = A.c2v + cell * (D + 1);
 #pragma unroll
-    for (int v = 0; v <= D; ++v) {
-        const int64_t gv = cv[v];
+    for (int v = 0; v <= D; ++v) ix.v[v] = __builtin_nontemporal_load(cv + v);
+    if constexpr (FD > 0) {
+        if (A.f0.map) {
+            const int32_t* m = A.f0.map + cell * NF;
 #pragma unroll
-        for (int i = 0; i < D; ++i) x[v][i] = A.coords[gv * D + i];
+            for (int r = 0; r < NF; ++r) ix.f0[r] = __builtin_nontemporal_load(m + r);
+        }
+        if constexpr (FORM == F_ELAST) {
+            if (A.f1.map) {
+                const int32_t* m = A.f1.map + cell * NF;
+#pragma unroll
+                for (int r = 0; r < NF; ++r) ix.f1[r] = __builtin_nontemporal_load(m + r);
+            }
+        }
     }
+}
+
+template <int NL, int NCOMP>
+__device__ inline void load_field_vals(const FieldArg& f, int64_t cell, const int* idx, double* v) {
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int64_t base = f.map ? (int64_t)idx[r] * NCOMP : (cell * NL + r) * NCOMP;
+#pragma unroll
+        for (int c = 0; c < NCOMP; ++c) v[r * NCOMP + c] = f.values[base + c];
+    }
+}
+
+template <int FORM, int D, int FD>
+__device__ inline void load_raw(const LinArgs& A, int64_t cell, const CellIdx<FORM, D, FD>& ix,
+                                CellRaw<FORM, D, FD>& rw) {
+    constexpr int NF = nfield(D, FD);
+#pragma unroll
+    for (int v = 0; v <= D; ++v)
+#pragma unroll
+        for (int i = 0; i < D; ++i) rw.x[v][i] = A.coords[(int64_t)ix.v[v] * D + i];
+    if constexpr (FD > 0) {
+        load_field_vals<NF, CellRaw<FORM, D, FD>::WC>(A.f0, cell, ix.f0, rw.f0);
+        if constexpr (FORM == F_ELAST) load_field_vals<NF, 1>(A.f1, cell, ix.f1, rw.f1);
+    }
+}
+
+template <int D>
+__device__ inline void geometry_from_coords(const double (&x)[D + 1][D], Geom<D>& g) {
     double J[D][D];
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -101,7 +159,6 @@ __device__ inline void load_geometry(const LinArgs& A, int64_t cell, Geom<D>& g)
         const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
         const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
         const double r = 1.0 / det;
-        // K = adj(J) / det, adj(J)[i][j] = cofactor(J)[j][i]
         g.K[0][0] = c00 * r;
         g.K[1][0] = c01 * r;
         g.K[2][0] = c02 * r;
@@ -112,16 +169,6 @@ __device__ inline void load_geometry(const LinArgs& A, int64_t cell, Geom<D>& g)
         g.K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
         g.K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
         g.adet = fabs(det);
-    }
-}
-
-template <int NL, int NCOMP>
-__device__ inline void load_field(const FieldArg& f, int64_t cell, double (&v)[NL * NCOMP]) {
-#pragma unroll
-    for (int r = 0; r < NL; ++r) {
-        const int64_t base = f.map ? (int64_t)f.map[cell * NL + r] * NCOMP : (cell * NL + r) * NCOMP;
-#pragma unroll
-        for (int c = 0; c < NCOMP; ++c) v[r * NCOMP + c] = f.values[base + c];
     }
 }
 
@@ -138,13 +185,25 @@ struct CellData {
 };
 
 template <int FORM, int D, int FD>
-__device__ inline void load_cell(const LinArgs& A, int64_t cell, CellData<FORM, D, FD>& cd) {
-    load_geometry<D>(A, cell, cd.g);
-    constexpr int NF = nfield(D, FD);
+__device__ inline void cell_from_raw(const CellRaw<FORM, D, FD>& rw, CellData<FORM, D, FD>& cd) {
+    geometry_from_coords<D>(rw.x, cd.g);
     if constexpr (FD > 0) {
-        load_field<NF, CellData<FORM, D, FD>::WC>(A.f0, cell, cd.f0);
-        if constexpr (FORM == F_ELAST) load_field<NF, 1>(A.f1, cell, cd.f1);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(cd.f0) / sizeof(double)); ++i) cd.f0[i] = rw.f0[i];
+        if constexpr (FORM == F_ELAST) {
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(cd.f1) / sizeof(double)); ++i) cd.f1[i] = rw.f1[i];
+        }
     }
+}
+
+template <int FORM, int D, int FD>
+__device__ inline void load_cell(const LinArgs& A, int64_t cell, CellData<FORM, D, FD>& cd) {
+    CellIdx<FORM, D, FD> ix;
+    CellRaw<FORM, D, FD> rw;
+    load_idx<FORM, D, FD>(A, cell, ix);
+    load_raw<FORM, D, FD>(A, cell, ix, rw);
+    cell_from_raw<FORM, D, FD>(rw, cd);
 }
 
 // G[k] of block (c1, c2) in the tensor order of reference.cpp.
@@ -283,12 +342,6 @@ __device__ inline typename PrecT<PREC>::frag load_afrag(const typename PrecT<PRE
     }
 }
 
-template <int PREC>
-__device__ inline void store_out(typename PrecT<PREC>::otype* p, typename PrecT<PREC>::otype v, int nt) {
-    if (nt) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-
 // Contract one block of the wave's 64 cells and store it.
 template <int FORM, int D, int P, int FD, int PREC, int C1, int C2>
 __device__ inline void contract_block(const LinArgs& A, const typename PrecT<PREC>::gtype* wtile,
@@ -349,7 +402,7 @@ __device__ inline void contract_block(const LinArgs& A, const typename PrecT<PRE
                 for (int v = 0; v < 4; ++v) {
                     const int64_t cell = wave_base + j * 16 + acc_row<PREC>(lane, v);
                     if (cell < A.ncells)
-                        store_out<PREC>(out + cell * (int64_t)N * N + off_in_cell, (out_t)acc[t][v], A.nontemporal);
+                        out[cell * (int64_t)N * N + off_in_cell] = (out_t)acc[t][v];
                 }
             }
         }

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "linear.hpp"
+#include "scalar.hpp"
 
 namespace coffee {
 
@@ -17,16 +18,30 @@ struct LinEntry {
     const void* kernel;
 };
 
+// Mass and Helmholtz are symmetric single-block forms and use the symmetric
+// engine (scalar.hpp); the vector forms use the block engine (linear.hpp).
+constexpr bool uses_scalar_engine(int form) { return form == dev::F_MASS || form == dev::F_HELM; }
+
+template <int FORM, int D, int P, int FD, int PREC>
+const void* kernel_of() {
+    if constexpr (uses_scalar_engine(FORM))
+        return reinterpret_cast<const void*>(&dev::k_scalar<FORM, D, P, FD, PREC>);
+    else
+        return reinterpret_cast<const void*>(&dev::k_linear<FORM, D, P, FD, PREC>);
+}
+
 template <int FORM, int D, int P, int FD, int PREC>
 hipError_t launch_linear(const dev::LinArgs& a, hipStream_t s, int grid) {
-    hipLaunchKernelGGL((dev::k_linear<FORM, D, P, FD, PREC>), dim3(grid), dim3(256), 0, s, a);
+    if constexpr (uses_scalar_engine(FORM))
+        hipLaunchKernelGGL((dev::k_scalar<FORM, D, P, FD, PREC>), dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((dev::k_linear<FORM, D, P, FD, PREC>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 template <int FORM, int D, int P, int FD, int PREC>
 LinEntry lin_entry() {
-    return LinEntry{FORM, D, P, FD, PREC, &launch_linear<FORM, D, P, FD, PREC>,
-                    reinterpret_cast<const void*>(&dev::k_linear<FORM, D, P, FD, PREC>)};
+    return LinEntry{FORM, D, P, FD, PREC, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>()};
 }
 
 // one instance for each precision
