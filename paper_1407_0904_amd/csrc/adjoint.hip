@@ -1,0 +1,316 @@
+// Reverse mode of the linear-form assembly.
+//
+// For a bilinear form the per-cell functional S_e = lam_e^T A_e u_e equals
+// sum_blk sum_k G^blk_k T^blk_k with T^blk_k = lam_{c1}^T R_k u_{c2}: the
+// reference tensors are contracted with the test and trial vectors once, and
+// the geometry tensor G carries every dependence on the cell. Its derivatives
+// are taken with forward-mode dual numbers through the same G builder the
+// forward kernels use, seeded on each entry of K = J^-1 and on each local
+// coefficient dof; every term of G is linear in |det J|, so
+// dS/d|det J| = S / |det J|. The chain to the vertex coordinates is analytic:
+//     dK = -K dJ K  ->  Jbar = -K^T Kbar K^T,
+//     d|det J| = |det J| tr(K dJ)  ->  Jbar += Sbar_adet |det J| K^T,
+//     J = [x1 - x0, ..., xd - x0]  ->  xbar_{j+1} = Jbar[:, j], xbar_0 = -sum_j Jbar[:, j].
+// One thread per cell; gradients are scatter-added with FP64 atomics.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "library.h"
+#include "linear.hpp"
+#include "tables.h"
+
+namespace coffee {
+namespace dev {
+
+struct AdjArgs {
+    LinArgs L;               // mesh, fields, constants (rfrag/out unused)
+    const double* R;         // reference tensors [KR][NS * NS]
+    const double* lam;       // [E][N]
+    const double* u;         // [E][N]
+    double seed;
+    double* grad_coords;     // [V][D]
+    double* grad_f0;         // shaped like f0 values, or NULL
+    double* grad_f1;
+    double* cell_value;      // [E] or NULL
+};
+
+template <int FORM, int D, int FD>
+struct AdjDirs {
+    static constexpr int NF = nfield(D, FD);
+    static constexpr int WC = (FORM == F_BURG) ? D : 1;
+    static constexpr int N0 = FD > 0 ? NF * WC : 0;                      // field 0 dofs
+    static constexpr int N1 = (FORM == F_ELAST && FD > 0) ? NF : 0;      // field 1 dofs
+};
+
+// Accumulate the contribution of block B: value, Kbar and coefficient bars.
+template <int FORM, int D, int P, int FD, int B>
+__device__ inline void adjoint_block(const AdjArgs& A, const double* Rs, const CellData<FORM, D, FD, double>& cd,
+                                     const double* lam_e,
+                                     const double* u_e, double& S, double (&Kbar)[D][D], double* f0bar,
+                                     double* f1bar) {
+    constexpr int NS = nsc(D, P), NN = NS * NS;
+    constexpr int NC = ncomp_space(FORM, D);
+    constexpr int C1 = B / NC, C2 = B % NC;
+    // the block's rows of lam_e and u_e (re-read per block from the L1 cache)
+    double lam[NS], u[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        lam[i] = lam_e[C1 * NS + i];
+        u[i] = u_e[C2 * NS + i];
+    }
+    // gbar(k) = T_k = lam_c1^T R_k u_c2 (R_k read with wave-uniform addresses)
+    auto gbar = [&](int k) -> double {
+        // keeps the compiler from hoisting every R_k load of the block into
+        // registers at once
+        asm volatile("" ::: "memory");
+        const double* Rk = Rs + (size_t)k * NN;
+        double t = 0.0;
+#pragma unroll 1
+        for (int a = 0; a < NS; ++a) {
+            double r = 0.0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) r += Rk[a * NS + b] * u[b];
+            t += lam[a] * r;
+        }
+        return t;
+    };
+    reverse_G<FORM, D, FD, C1, C2>(cd, A.L, gbar, S, Kbar, f0bar, f1bar);
+}
+
+// One block per iteration of a runtime loop, so that the compiler keeps one
+// block's temporaries live at a time.
+template <int FORM, int D, int P, int FD, int B, int NB>
+__device__ inline void adjoint_block_switch(int b, const AdjArgs& A, const double* Rs,
+                                            const CellData<FORM, D, FD, double>& cd, const double* lam,
+                                            const double* u, double& S, double (&Kbar)[D][D], double* f0bar,
+                                            double* f1bar) {
+    if constexpr (B < NB) {
+        if (b == B) adjoint_block<FORM, D, P, FD, B>(A, Rs, cd, lam, u, S, Kbar, f0bar, f1bar);
+        else adjoint_block_switch<FORM, D, P, FD, B + 1, NB>(b, A, Rs, cd, lam, u, S, Kbar, f0bar, f1bar);
+    }
+}
+
+template <int FORM, int D, int P, int FD, int NB>
+__device__ inline void adjoint_blocks(const AdjArgs& A, const double* Rs, const CellData<FORM, D, FD, double>& cd,
+                                      const double* lam, const double* u, double& S, double (&Kbar)[D][D],
+                                      double* f0bar, double* f1bar) {
+#pragma unroll 1
+    for (int b = 0; b < NB; ++b)
+        adjoint_block_switch<FORM, D, P, FD, 0, NB>(b, A, Rs, cd, lam, u, S, Kbar, f0bar, f1bar);
+}
+
+// Reference tensors of the adjoint kernels live in LDS when they fit.
+template <int FORM, int D, int P, int FD>
+constexpr int adj_r_elems() { return kref(FORM, D, FD) * nsc(D, P) * nsc(D, P); }
+template <int FORM, int D, int P, int FD>
+constexpr bool adj_r_in_lds() { return adj_r_elems<FORM, D, P, FD>() * 8 <= 56 * 1024; }
+
+template <int FORM, int D, int P, int FD>
+__global__ __launch_bounds__(256) void k_adjoint_linear(AdjArgs A) {
+    constexpr int NS = nsc(D, P);
+    constexpr int NC = ncomp_space(FORM, D);
+    constexpr int N = NC * NS;
+    using Dirs = AdjDirs<FORM, D, FD>;
+    constexpr bool LDSR = adj_r_in_lds<FORM, D, P, FD>();
+    constexpr int RE = adj_r_elems<FORM, D, P, FD>();
+    __shared__ double sR[LDSR ? RE : 1];
+    const double* Rs = A.R;
+    if constexpr (LDSR) {
+        for (int i = threadIdx.x; i < RE; i += blockDim.x) sR[i] = A.R[i];
+        __syncthreads();
+        Rs = sR;
+    }
+    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.L.ncells;
+         cell += (int64_t)gridDim.x * blockDim.x) {
+        CellIdx<FORM, D, FD> ix;
+        CellRaw<FORM, D, FD> raw;
+        load_idx<FORM, D, FD>(A.L, cell, ix);
+        load_raw<FORM, D, FD>(A.L, cell, ix, raw);
+        CellData<FORM, D, FD, double> cd;
+        cell_from_raw<FORM, D, FD>(raw, cd);
+        const double* lam = A.lam + cell * N;
+        const double* u = A.u + cell * N;
+        double S = 0.0, Kbar[D][D];
+        double f0bar[Dirs::N0 > 0 ? Dirs::N0 : 1], f1bar[Dirs::N1 > 0 ? Dirs::N1 : 1];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Kbar[i][j] = 0.0;
+#pragma unroll
+        for (int r = 0; r < (Dirs::N0 > 0 ? Dirs::N0 : 1); ++r) f0bar[r] = 0.0;
+#pragma unroll
+        for (int r = 0; r < (Dirs::N1 > 0 ? Dirs::N1 : 1); ++r) f1bar[r] = 0.0;
+        adjoint_blocks<FORM, D, P, FD, NC * NC>(A, Rs, cd, lam, u, S, Kbar, f0bar, f1bar);
+        if (A.cell_value) A.cell_value[cell] = S;
+
+        // chain to the coordinates
+        const auto& K = cd.g.K;
+        const double adbar_ad = S;  // d S / d|det J| * |det J|
+        double Jbar[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                // -(K^T Kbar K^T)_ij = -sum_ab K[a][i] Kbar[a][b] K[j][b]
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) s += K[a][i] * Kbar[a][b] * K[j][b];
+                Jbar[i][j] = -s + adbar_ad * K[j][i];
+            }
+        const double sd = A.seed;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double x0 = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                atomicAdd(A.grad_coords + (int64_t)ix.v[j + 1] * D + i, sd * Jbar[i][j]);
+                x0 -= Jbar[i][j];
+            }
+            atomicAdd(A.grad_coords + (int64_t)ix.v[0] * D + i, sd * x0);
+        }
+        if constexpr (Dirs::N0 > 0) {
+            if (A.grad_f0) {
+                constexpr int NF = Dirs::NF, WC = Dirs::WC;
+#pragma unroll
+                for (int r = 0; r < NF; ++r) {
+                    const int64_t base = A.L.f0.map ? (int64_t)ix.f0[r] * WC : (cell * NF + r) * WC;
+#pragma unroll
+                    for (int c = 0; c < WC; ++c) atomicAdd(A.grad_f0 + base + c, sd * f0bar[r * WC + c]);
+                }
+            }
+        }
+        if constexpr (Dirs::N1 > 0) {
+            if (A.grad_f1) {
+                constexpr int NF = Dirs::NF;
+#pragma unroll
+                for (int r = 0; r < NF; ++r) {
+                    const int64_t base = A.L.f1.map ? (int64_t)ix.f1[r] : cell * NF + r;
+                    atomicAdd(A.grad_f1 + base, sd * f1bar[r]);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace dev
+
+typedef hipError_t (*AdjLaunch)(const dev::AdjArgs&, hipStream_t, int grid);
+struct AdjEntry {
+    int form, dim, p, fd;
+    AdjLaunch launch;
+};
+
+template <int FORM, int D, int P, int FD>
+hipError_t launch_adjoint(const dev::AdjArgs& a, hipStream_t s, int grid) {
+    hipLaunchKernelGGL((dev::k_adjoint_linear<FORM, D, P, FD>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+static const std::vector<AdjEntry>& adj_registry() {
+    using namespace dev;
+    static const std::vector<AdjEntry> reg = {
+        {F_MASS, 2, 1, 1, &launch_adjoint<F_MASS, 2, 1, 1>},
+        {F_MASS, 3, 1, 1, &launch_adjoint<F_MASS, 3, 1, 1>},
+        {F_MASS, 3, 2, 2, &launch_adjoint<F_MASS, 3, 2, 2>},
+        {F_HELM, 2, 1, 1, &launch_adjoint<F_HELM, 2, 1, 1>},
+        {F_HELM, 2, 2, 1, &launch_adjoint<F_HELM, 2, 2, 1>},
+        {F_HELM, 3, 1, 1, &launch_adjoint<F_HELM, 3, 1, 1>},
+        {F_HELM, 3, 2, 2, &launch_adjoint<F_HELM, 3, 2, 2>},
+        {F_ELAST, 2, 1, 1, &launch_adjoint<F_ELAST, 2, 1, 1>},
+        {F_ELAST, 2, 2, 1, &launch_adjoint<F_ELAST, 2, 2, 1>},
+        {F_ELAST, 3, 1, 1, &launch_adjoint<F_ELAST, 3, 1, 1>},
+        {F_ELAST, 3, 2, 1, &launch_adjoint<F_ELAST, 3, 2, 1>},
+        {F_BURG, 2, 1, 1, &launch_adjoint<F_BURG, 2, 1, 1>},
+        {F_BURG, 3, 1, 1, &launch_adjoint<F_BURG, 3, 1, 1>},
+        {F_BURG, 3, 2, 2, &launch_adjoint<F_BURG, 3, 2, 2>},
+    };
+    return reg;
+}
+
+static std::mutex g_adj_mu;
+static std::map<std::tuple<int, int, int, int, int, int>, void*> g_adj_tables;  // (dev, form, dim, p, q, fd)
+
+static coffee_status adjoint_table(int dev, int form, int dim, int p, int q, int fd, const double** out) {
+    std::lock_guard<std::mutex> lk(g_adj_mu);
+    auto key = std::make_tuple(dev, form, dim, p, q, fd);
+    auto it = g_adj_tables.find(key);
+    if (it != g_adj_tables.end()) {
+        *out = (const double*)it->second;
+        return COFFEE_OK;
+    }
+    RefTensor R;
+    if (!build_reference(form, dim, p, q, fd, R)) return COFFEE_E_INVALID_ARG;
+    std::vector<double> h(R.R.size());
+    for (size_t i = 0; i < h.size(); ++i) h[i] = (double)R.R[i];
+    void* d = nullptr;
+    if (hipMalloc(&d, h.size() * sizeof(double)) != hipSuccess) return COFFEE_E_NOMEM;
+    if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return COFFEE_E_HIP;
+    }
+    g_adj_tables[key] = d;
+    *out = (const double*)d;
+    return COFFEE_OK;
+}
+
+void free_adjoint_tables() {
+    std::lock_guard<std::mutex> lk(g_adj_mu);
+    for (auto& kv : g_adj_tables) {
+        (void)hipSetDevice(std::get<0>(kv.first));
+        (void)hipFree(kv.second);
+    }
+    g_adj_tables.clear();
+}
+
+coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, const double* coords, int64_t nvert,
+                             const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, int ncoeff,
+                             const double* constants, int nconst, const double* lam, const double* u,
+                             double seed, double* grad_coords, double* const* grad_coeff_values,
+                             double* cell_value, void* hip_stream) {
+    const AdjEntry* e = nullptr;
+    for (const AdjEntry& x : adj_registry())
+        if (x.form == form && x.dim == cell && x.p == degree && x.fd == fd) e = &x;
+    if (!e) return COFFEE_E_UNSUPPORTED;
+    if (ncells > 0 && (!lam || !u || !grad_coords)) return COFFEE_E_INVALID_ARG;
+    if (ncells == 0) return COFFEE_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return COFFEE_E_HIP;
+    const double* R = nullptr;
+    coffee_status st = adjoint_table(dev, form, cell, degree, q, fd, &R);
+    if (st != COFFEE_OK) return st;
+    dev::AdjArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.L.coords = coords;
+    a.L.c2v = c2v;
+    a.L.ncells = ncells;
+    if (ncoeff >= 1) a.L.f0 = dev::FieldArg{coeffs[0].values, coeffs[0].cell_to_dof};
+    if (ncoeff >= 2) a.L.f1 = dev::FieldArg{coeffs[1].values, coeffs[1].cell_to_dof};
+    if (form == COFFEE_BURGERS) {
+        a.L.c0 = nconst > 0 ? constants[0] : 1.0;
+        a.L.c1 = nconst > 1 ? constants[1] : 1.0;
+    } else if (form == COFFEE_ELASTICITY && ncoeff == 0) {
+        a.L.c0 = constants[0];
+        a.L.c1 = constants[1];
+    }
+    a.R = R;
+    a.lam = lam;
+    a.u = u;
+    a.seed = seed;
+    a.grad_coords = grad_coords;
+    a.grad_f0 = (grad_coeff_values && ncoeff >= 1) ? grad_coeff_values[0] : nullptr;
+    a.grad_f1 = (grad_coeff_values && ncoeff >= 2) ? grad_coeff_values[1] : nullptr;
+    a.cell_value = cell_value;
+    const int64_t blocks = (ncells + 255) / 256;
+    const int grid = (int)std::min<int64_t>(blocks, (int64_t)num_cu(dev) * 8);
+    if (e->launch(a, (hipStream_t)hip_stream, grid) != hipSuccess) return COFFEE_E_HIP;
+    return COFFEE_OK;
+}
+
+}  // namespace coffee

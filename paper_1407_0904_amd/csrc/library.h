@@ -17,6 +17,13 @@ coffee_status assemble_svk(int form, int cell, int degree, int q, int precision,
                            const double* constants, int nconst, void* out, void* hip_stream);
 
 int grid_for(int dev, const void* kernel, int64_t nchunks, int default_mult);
+
+coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, const double* coords, int64_t nvert,
+                             const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, int ncoeff,
+                             const double* constants, int nconst, const double* lam, const double* u,
+                             double seed, double* grad_coords, double* const* grad_coeff_values,
+                             double* cell_value, void* hip_stream);
+void free_adjoint_tables();
 int num_cu(int dev);
 int blocks_per_cu(int dev, const void* kernel);
 

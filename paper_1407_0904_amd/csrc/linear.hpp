@@ -21,6 +21,8 @@
 
 #include <cstdint>
 
+#include "dual.hpp"
+
 namespace coffee {
 namespace dev {
 
@@ -65,10 +67,10 @@ struct LinArgs {
 
 // ---------------------------------------------------------------- geometry
 
-template <int D>
+template <int D, typename T = double>
 struct Geom {
-    double K[D][D];
-    double adet;
+    T K[D][D];
+    T adet;
 };
 
 // ---------------------------------------------------------------- split gathers
@@ -138,27 +140,27 @@ __device__ inline void load_raw(const LinArgs& A, int64_t cell, const CellIdx<FO
     }
 }
 
-template <int D>
-__device__ inline void geometry_from_coords(const double (&x)[D + 1][D], Geom<D>& g) {
-    double J[D][D];
+template <int D, typename T = double>
+__host__ __device__ inline void geometry_from_coords(const T (&x)[D + 1][D], Geom<D, T>& g) {
+    T J[D][D];
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j < D; ++j) J[i][j] = x[j + 1][i] - x[0][i];
     if constexpr (D == 2) {
-        const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        const double r = 1.0 / det;
+        const T det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const T r = 1.0 / det;
         g.K[0][0] = J[1][1] * r;
         g.K[0][1] = -J[0][1] * r;
         g.K[1][0] = -J[1][0] * r;
         g.K[1][1] = J[0][0] * r;
-        g.adet = fabs(det);
+        g.adet = absval(det);
     } else {
-        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-        const double r = 1.0 / det;
+        const T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        const T det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        const T r = 1.0 / det;
         g.K[0][0] = c00 * r;
         g.K[1][0] = c01 * r;
         g.K[2][0] = c02 * r;
@@ -168,20 +170,20 @@ __device__ inline void geometry_from_coords(const double (&x)[D + 1][D], Geom<D>
         g.K[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
         g.K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
         g.K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
-        g.adet = fabs(det);
+        g.adet = absval(det);
     }
 }
 
 // ---------------------------------------------------------------- G per form
 
 // Cell data needed by the G builders.
-template <int FORM, int D, int FD>
+template <int FORM, int D, int FD, typename T = double>
 struct CellData {
     static constexpr int NF = nfield(D, FD);
     static constexpr int WC = (FORM == F_BURG) ? D : 1;
-    Geom<D> g;
-    double f0[FD > 0 ? NF * WC : 1];
-    double f1[(FORM == F_ELAST && FD > 0) ? NF : 1];
+    Geom<D, T> g;
+    T f0[FD > 0 ? NF * WC : 1];
+    T f1[(FORM == F_ELAST && FD > 0) ? NF : 1];
 };
 
 template <int FORM, int D, int FD>
@@ -207,23 +209,23 @@ __device__ inline void load_cell(const LinArgs& A, int64_t cell, CellData<FORM, 
 }
 
 // G[k] of block (c1, c2) in the tensor order of reference.cpp.
-template <int FORM, int D, int FD, int C1, int C2>
-__device__ inline void build_G(const CellData<FORM, D, FD>& cd, const LinArgs& A, double* G) {
+template <int FORM, int D, int FD, int C1, int C2, typename T = double>
+__host__ __device__ inline void build_G(const CellData<FORM, D, FD, T>& cd, const LinArgs& A, T* G) {
     constexpr int NF = nfield(D, FD);
     const auto& K = cd.g.K;
-    const double ad = cd.g.adet;
+    const T ad = cd.g.adet;
     int t = 0;
     if constexpr (FORM == F_HELM || FORM == F_BURG) {
-        const double sc = (FORM == F_BURG) ? ad * A.c0 : ad;  // nu for Burgers
-        if constexpr (FORM == F_BURG) G[t++] = (C1 == C2) ? ad * A.c1 : 0.0;
+        const T sc = (FORM == F_BURG) ? ad * A.c0 : ad;  // nu for Burgers
+        if constexpr (FORM == F_BURG) G[t++] = (C1 == C2) ? ad * A.c1 : T(0.0);
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
             for (int b = a; b < D; ++b) {
-                double s = 0.0;
+                T s = 0.0;
 #pragma unroll
                 for (int i = 0; i < D; ++i) s += K[a][i] * K[b][i];
-                G[t++] = (C1 == C2) ? sc * s : 0.0;
+                G[t++] = (C1 == C2) ? sc * s : T(0.0);
             }
     }
     if constexpr (FORM == F_MASS || FORM == F_HELM) {
@@ -232,13 +234,13 @@ __device__ inline void build_G(const CellData<FORM, D, FD>& cd, const LinArgs& A
     } else if constexpr (FORM == F_ELAST) {
 #pragma unroll
         for (int r = 0; r < NF; ++r) {
-            const double mu = (FD > 0) ? cd.f0[r] : A.c0;
-            const double lm = (FD > 0) ? cd.f1[r] : A.c1;
+            const T mu = (FD > 0) ? cd.f0[r] : T(A.c0);
+            const T lm = (FD > 0) ? cd.f1[r] : T(A.c1);
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
                 for (int b = 0; b < D; ++b) {
-                    double kk = 0.0;
+                    T kk = 0.0;
                     if constexpr (C1 == C2) {
 #pragma unroll
                         for (int i = 0; i < D; ++i) kk += K[a][i] * K[b][i];
@@ -252,16 +254,134 @@ __device__ inline void build_G(const CellData<FORM, D, FD>& cd, const LinArgs& A
         for (int r = 0; r < NF; ++r)
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                double s = 0.0;
+                T s = 0.0;
 #pragma unroll
                 for (int i = 0; i < D; ++i) s += cd.f0[r * D + i] * K[a][i];
-                G[t++] = (C1 == C2) ? ad * s : 0.0;
+                G[t++] = (C1 == C2) ? ad * s : T(0.0);
             }
         // E(r, a): |det J| w_{r,c1} K[a][c2]
 #pragma unroll
         for (int r = 0; r < NF; ++r)
 #pragma unroll
             for (int a = 0; a < D; ++a) G[t++] = ad * cd.f0[r * D + C1] * K[a][C2];
+    }
+}
+
+// Transpose of build_G: with gbar(k) = dS/dG[k] for block (c1, c2), add the
+// block's value sum_k G[k] gbar(k) to S, dS/dK to Kbar and dS/d(coefficient
+// dofs) to f0bar / f1bar. gbar is evaluated once per k. Every term of G has
+// exactly one factor |det J|, so dS/d|det J| = S / |det J| follows from S.
+template <int FORM, int D, int FD, int C1, int C2, typename GB>
+__host__ __device__ inline void reverse_G(const CellData<FORM, D, FD>& cd, const LinArgs& A, GB&& gbar, double& S,
+                                          double (&Kbar)[D][D], double* f0bar, double* f1bar) {
+    constexpr int NF = nfield(D, FD);
+    const auto& K = cd.g.K;
+    const double ad = cd.g.adet;
+    int t = 0;
+    if constexpr (FORM == F_HELM || FORM == F_BURG) {
+        const double sc = (FORM == F_BURG) ? ad * A.c0 : ad;
+        if constexpr (FORM == F_BURG) {
+            // (1/dt) |det J|: no K or coefficient dependence
+            if (C1 == C2) S += ad * A.c1 * gbar(t);
+            ++t;
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b) {
+                // G = sc sum_i K[a][i] K[b][i]
+                if (C1 == C2) {
+                    const double g = sc * gbar(t);
+                    double kk = 0.0;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        kk += K[a][i] * K[b][i];
+                        Kbar[a][i] += g * K[b][i];
+                        Kbar[b][i] += g * K[a][i];
+                    }
+                    S += g * kk;
+                }
+                ++t;
+            }
+    }
+    if constexpr (FORM == F_MASS || FORM == F_HELM) {
+#pragma unroll
+        for (int r = 0; r < NF; ++r) {
+            const double g = ad * gbar(t + r);
+            if constexpr (FD > 0) {
+                f0bar[r] += g;
+                S += g * cd.f0[r];
+            } else {
+                S += g;
+            }
+        }
+    } else if constexpr (FORM == F_ELAST) {
+#pragma unroll
+        for (int r = 0; r < NF; ++r) {
+            const double mu = (FD > 0) ? cd.f0[r] : A.c0;
+            const double lm = (FD > 0) ? cd.f1[r] : A.c1;
+            double mubar = 0.0, lmbar = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    // G = ad (mu (delta KK^T_ab + K[a][C2] K[b][C1]) + lm K[a][C1] K[b][C2])
+                    const double gb = ad * gbar(t++);
+                    double kk = 0.0;
+                    if constexpr (C1 == C2) {
+#pragma unroll
+                        for (int i = 0; i < D; ++i) kk += K[a][i] * K[b][i];
+                    }
+                    mubar += gb * (kk + K[a][C2] * K[b][C1]);
+                    lmbar += gb * K[a][C1] * K[b][C2];
+                    const double gm = gb * mu, gl = gb * lm;
+                    if constexpr (C1 == C2) {
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            Kbar[a][i] += gm * K[b][i];
+                            Kbar[b][i] += gm * K[a][i];
+                        }
+                    }
+                    Kbar[a][C2] += gm * K[b][C1];
+                    Kbar[b][C1] += gm * K[a][C2];
+                    Kbar[a][C1] += gl * K[b][C2];
+                    Kbar[b][C2] += gl * K[a][C1];
+                }
+            S += mu * mubar + lm * lmbar;
+            if constexpr (FD > 0) {
+                f0bar[r] += mubar;
+                f1bar[r] += lmbar;
+            }
+        }
+    } else if constexpr (FORM == F_BURG) {
+        // C(r, a) = delta ad sum_i w_{r,i} K[a][i]
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                if (C1 == C2) {
+                    const double g = ad * gbar(t);
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        s += cd.f0[r * D + i] * K[a][i];
+                        Kbar[a][i] += g * cd.f0[r * D + i];
+                        f0bar[r * D + i] += g * K[a][i];
+                    }
+                    S += g * s;
+                }
+                ++t;
+            }
+        // E(r, a) = ad w_{r,c1} K[a][c2]
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double g = ad * gbar(t++);
+                Kbar[a][C2] += g * cd.f0[r * D + C1];
+                f0bar[r * D + C1] += g * K[a][C2];
+                S += g * cd.f0[r * D + C1] * K[a][C2];
+            }
     }
 }
 
