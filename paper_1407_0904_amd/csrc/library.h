@@ -24,6 +24,7 @@ coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, cons
                              double seed, double* grad_coords, double* const* grad_coeff_values,
                              double* cell_value, void* hip_stream);
 void free_adjoint_tables();
+void free_svk_tables();
 int num_cu(int dev);
 int blocks_per_cu(int dev, const void* kernel);
 

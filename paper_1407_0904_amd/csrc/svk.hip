@@ -1,11 +1,582 @@
-// St Venant-Kirchhoff hyperelasticity: energy, residual and Jacobian.
+// St Venant-Kirchhoff hyperelasticity: energy, residual and Jacobian, and the
+// reverse pass of the energy.
+//
+// Per quadrature point (the paper's section 2 kernel structure, with the
+// coefficient evaluated at the point as in Listing 2): the displacement
+// gradient grad u = U K (U[i][a] = sum_r u_{r,i} dphi_r/dX_a in reference
+// coordinates), F = I + grad u, E = (F^T F - I)/2, S = lambda tr(E) I + 2 mu E,
+// P = F S, psi = lambda/2 tr(E)^2 + mu E:E. Then
+//   energy   Pi_e = sum_q w_q |det J| psi
+//   residual b_(c,a) = sum_q w_q |det J| sum_j P_cj dphi_a/dx_j
+//   Jacobian A_(c,a),(c',b) = sum_q w_q |det J| sum_jl dphi_a/dx_j C_cjc'l dphi_b/dx_l,
+// with the tangent C_cjc'l = delta_cc' S_lj + lambda F_cj F_c'l + mu F_cl F_c'j
+// + mu delta_lj (F F^T)_cc' (the derivative of P along e_c' (x) e_l). In
+// reference coordinates the Jacobian block is sum_q sum_ab dphi_a/dX_a H_ab
+// dphi_b/dX_b with H = w |det J| K C K^T, accumulated as two rank-structured
+// updates per point and reference direction.
+//
+// Work layout: energy and residual one thread per cell; Jacobian one thread per
+// (cell, block c <= c') holding that block's n x n accumulators, the mirrored
+// block written from the same values (the Jacobian is symmetric). Reference
+// gradients and weights are staged in LDS and read at wave-uniform addresses.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "library.h"
+#include "linear.hpp"
+#include "tables.h"
 
 namespace coffee {
+namespace dev {
 
-coffee_status assemble_svk(int, int, int, int, int, const double*, int64_t, const int32_t*, int64_t,
-                           const coffee_field*, const double*, int, void*, void*) {
-    return COFFEE_E_UNSUPPORTED;
+struct SvkArgs {
+    const double* coords;
+    const int32_t* c2v;
+    int64_t ncells;
+    FieldArg u;          // displacement, ncomp = D
+    double mu, lambda;
+    const double* tab;   // W[nq] then dphi[D][nq][NS]
+    void* out;
+    // reverse pass of the energy
+    double seed;
+    double* grad_coords;
+    double* grad_u;
+    double* cell_value;
+};
+
+template <int D>
+struct SvkPoint {
+    double F[D][D], S[D][D];
+};
+
+// F and S at point q from the reference displacement gradient.
+template <int D, int NS>
+__device__ inline void svk_point(const double (&uv)[NS * D], const double (&K)[D][D], const double* dphi_q, int nq,
+                                 double mu, double lm, SvkPoint<D>& pt, double* psi, double (&Pout)[D][D]) {
+    double U[D][D];  // U[i][a] = sum_r u_{r,i} dphi_r/dX_a
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < NS; ++r) s += uv[r * D + i] * dphi_q[(size_t)a * nq * NS + r];
+            U[i][a] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double g = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) g += U[i][a] * K[a][j];
+            pt.F[i][j] = (i == j ? 1.0 : 0.0) + g;
+        }
+    double E[D][D], trE = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) t += pt.F[k][i] * pt.F[k][j];
+            E[i][j] = 0.5 * (t - (i == j ? 1.0 : 0.0));
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) trE += E[i][i];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) pt.S[i][j] = (i == j ? lm * trE : 0.0) + 2.0 * mu * E[i][j];
+    if (psi) {
+        double EE = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) EE += E[i][j] * E[i][j];
+        *psi = 0.5 * lm * trE * trE + mu * EE;
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) t += pt.F[i][k] * pt.S[k][j];
+            Pout[i][j] = t;
+        }
+}
+
+template <int D, int NS>
+__device__ inline void svk_load(const SvkArgs& A, int64_t cell, Geom<D>& g, double (&uv)[NS * D],
+                                int (&vid)[D + 1], int (&uid)[NS]) {
+    double x[D + 1][D];
+#pragma unroll
+    for (int v = 0; v <= D; ++v) vid[v] = A.c2v[cell * (D + 1) + v];
+#pragma unroll
+    for (int v = 0; v <= D; ++v)
+#pragma unroll
+        for (int i = 0; i < D; ++i) x[v][i] = A.coords[(int64_t)vid[v] * D + i];
+    geometry_from_coords<D>(x, g);
+    if (A.u.map) {
+#pragma unroll
+        for (int r = 0; r < NS; ++r) uid[r] = A.u.map[cell * NS + r];
+    }
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+        const int64_t base = A.u.map ? (int64_t)uid[r] * D : (cell * NS + r) * D;
+#pragma unroll
+        for (int i = 0; i < D; ++i) uv[r * D + i] = A.u.values[base + i];
+    }
+}
+
+template <int D, int P>
+constexpr int svk_tab_elems(int nq) { return nq + D * nq * nsc(D, P); }
+
+// MODE 0: energy, 1: residual, 2: reverse pass of the energy.
+template <int D, int P, int NQ, int MODE, typename OT>
+__global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
+    constexpr int NS = nsc(D, P);
+    constexpr int TE = NQ + D * NQ * NS;
+    __shared__ double tab[TE];
+    for (int i = threadIdx.x; i < TE; i += blockDim.x) tab[i] = A.tab[i];
+    __syncthreads();
+    const double* W = tab;
+    const double* dphi = tab + NQ;
+    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.ncells;
+         cell += (int64_t)gridDim.x * blockDim.x) {
+        Geom<D> g;
+        double uv[NS * D];
+        int vid[D + 1], uid[NS];
+        svk_load<D, NS>(A, cell, g, uv, vid, uid);
+        double energy = 0.0;
+        double res[MODE == 1 ? D * NS : 1];
+        double Kbar[D][D];  // reverse pass: d Pi / d K
+        if constexpr (MODE == 1) {
+#pragma unroll
+            for (int i = 0; i < D * NS; ++i) res[i] = 0.0;
+        }
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) Kbar[i][j] = 0.0;
+        }
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+            SvkPoint<D> pt;
+            double psi, Pm[D][D];
+            svk_point<D, NS>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, &psi, Pm);
+            const double wq = W[q];
+            energy += wq * psi;
+            if constexpr (MODE == 1) {
+                // b_(c,a) += w sum_al (P K^T)_c,al dphi_a/dX_al
+                double Q[D][D];
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+#pragma unroll
+                    for (int al = 0; al < D; ++al) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int j = 0; j < D; ++j) t += Pm[c][j] * g.K[al][j];
+                        Q[c][al] = wq * t;
+                    }
+#pragma unroll
+                for (int a = 0; a < NS; ++a) {
+                    double dp[D];
+#pragma unroll
+                    for (int al = 0; al < D; ++al) dp[al] = dphi[(size_t)al * NQ * NS + q * NS + a];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int al = 0; al < D; ++al) t += Q[c][al] * dp[al];
+                        res[c * NS + a] += t;
+                    }
+                }
+            }
+            if constexpr (MODE == 2) {
+                // d Pi / d K[al][j] = |det J| sum_q w sum_i P_ij U_i,al
+                double U[D][D];
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int al = 0; al < D; ++al) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int r = 0; r < NS; ++r) s += uv[r * D + i] * dphi[(size_t)al * NQ * NS + q * NS + r];
+                        U[i][al] = s;
+                    }
+#pragma unroll
+                for (int al = 0; al < D; ++al)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) s += Pm[i][j] * U[i][al];
+                        Kbar[al][j] += wq * s;
+                    }
+            }
+        }
+        const double ad = g.adet;
+        if constexpr (MODE == 0) {
+            reinterpret_cast<OT*>(A.out)[cell] = (OT)(ad * energy);
+        } else if constexpr (MODE == 1) {
+            OT* o = reinterpret_cast<OT*>(A.out) + cell * (D * NS);
+#pragma unroll
+            for (int i = 0; i < D * NS; ++i) o[i] = (OT)(ad * res[i]);
+        } else {
+            const double Pi = ad * energy;
+            if (A.cell_value) A.cell_value[cell] = Pi;
+            // Kbar scaled by |det J|; d Pi/d|det J| |det J| = Pi
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) Kbar[i][j] *= ad;
+            double Jbar[D][D];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+#pragma unroll
+                        for (int b = 0; b < D; ++b) s += g.K[a][i] * Kbar[a][b] * g.K[j][b];
+                    Jbar[i][j] = -s + Pi * g.K[j][i];
+                }
+            const double sd = A.seed;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double x0 = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    atomicAdd(A.grad_coords + (int64_t)vid[j + 1] * D + i, sd * Jbar[i][j]);
+                    x0 -= Jbar[i][j];
+                }
+                atomicAdd(A.grad_coords + (int64_t)vid[0] * D + i, sd * x0);
+            }
+        }
+    }
+}
+
+// Residual with scatter of seed * b_e into grad_u (the energy's u-gradient).
+template <int D, int P, int NQ>
+__global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
+    constexpr int NS = nsc(D, P);
+    constexpr int TE = NQ + D * NQ * NS;
+    __shared__ double tab[TE];
+    for (int i = threadIdx.x; i < TE; i += blockDim.x) tab[i] = A.tab[i];
+    __syncthreads();
+    const double* W = tab;
+    const double* dphi = tab + NQ;
+    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.ncells;
+         cell += (int64_t)gridDim.x * blockDim.x) {
+        Geom<D> g;
+        double uv[NS * D];
+        int vid[D + 1], uid[NS];
+        svk_load<D, NS>(A, cell, g, uv, vid, uid);
+        double res[D * NS];
+#pragma unroll
+        for (int i = 0; i < D * NS; ++i) res[i] = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+            SvkPoint<D> pt;
+            double Pm[D][D];
+            svk_point<D, NS>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, nullptr, Pm);
+            double Q[D][D];
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int al = 0; al < D; ++al) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) t += Pm[c][j] * g.K[al][j];
+                    Q[c][al] = W[q] * t;
+                }
+#pragma unroll
+            for (int a = 0; a < NS; ++a)
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int al = 0; al < D; ++al) t += Q[c][al] * dphi[(size_t)al * NQ * NS + q * NS + a];
+                    res[c * NS + a] += t;
+                }
+        }
+        const double f = A.seed * g.adet;
+#pragma unroll
+        for (int r = 0; r < NS; ++r) {
+            const int64_t base = A.u.map ? (int64_t)uid[r] * D : (cell * NS + r) * D;
+#pragma unroll
+            for (int c = 0; c < D; ++c) atomicAdd(A.grad_u + base + c, f * res[c * NS + r]);
+        }
+    }
+}
+
+// Jacobian: one thread per (cell, block c1 <= c2).
+template <int D, int P, int NQ, typename AT>
+__global__ __launch_bounds__(256) void k_svk_jacobian(SvkArgs A) {
+    constexpr int NS = nsc(D, P);
+    constexpr int N = D * NS;
+    constexpr int NB = D * (D + 1) / 2;
+    constexpr int CPW = 64 / NB;  // cells per wave
+    constexpr int TE = NQ + D * NQ * NS;
+    __shared__ double tab[TE];
+    for (int i = threadIdx.x; i < TE; i += blockDim.x) tab[i] = A.tab[i];
+    __syncthreads();
+    const double* W = tab;
+    const double* dphi = tab + NQ;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int blk = lane % NB, cl = lane / NB;
+    int c1 = 0, c2 = 0;
+    {
+        int t = blk;
+        while (t >= D - c1) { t -= D - c1; ++c1; }
+        c2 = c1 + t;
+    }
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t w0 = (int64_t)blockIdx.x * 4 + wave; w0 * CPW < A.ncells; w0 += nwaves) {
+        const int64_t cell = w0 * CPW + cl;
+        if (cl >= CPW || cell >= A.ncells) continue;
+        Geom<D> g;
+        double uv[NS * D];
+        int vid[D + 1], uid[NS];
+        svk_load<D, NS>(A, cell, g, uv, vid, uid);
+        AT acc[NS][NS];
+#pragma unroll
+        for (int a = 0; a < NS; ++a)
+#pragma unroll
+            for (int b = 0; b < NS; ++b) acc[a][b] = (AT)0;
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+            SvkPoint<D> pt;
+            double Pm[D][D];
+            svk_point<D, NS>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, nullptr, Pm);
+            // rows c1 and c2 of F (selected without lane-dependent register indexing)
+            double F1[D], F2[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                F1[k] = pt.F[0][k];
+                F2[k] = pt.F[0][k];
+            }
+#pragma unroll
+            for (int i = 1; i < D; ++i)
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    F1[k] = (c1 == i) ? pt.F[i][k] : F1[k];
+                    F2[k] = (c2 == i) ? pt.F[i][k] : F2[k];
+                }
+            // tangent block C[j][l] = C_(c1 j c2 l)
+            double FF = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) FF += F1[k] * F2[k];
+            double C[D][D];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+#pragma unroll
+                for (int l = 0; l < D; ++l)
+                    C[j][l] = (c1 == c2 ? pt.S[l][j] : 0.0) + A.lambda * F1[j] * F2[l] + A.mu * F1[l] * F2[j] +
+                              (j == l ? A.mu * FF : 0.0);
+            // H = w K C K^T (the |det J| factor is applied at the end)
+            double KC[D][D], H[D][D];
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int l = 0; l < D; ++l) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) s += g.K[a][j] * C[j][l];
+                    KC[a][l] = s;
+                }
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int l = 0; l < D; ++l) s += KC[a][l] * g.K[b][l];
+                    H[a][b] = W[q] * s;
+                }
+            // acc[a][b] += sum_al dphi_al,a (sum_be H[al][be] dphi_be,b)
+#pragma unroll
+            for (int al = 0; al < D; ++al) {
+                AT v[NS];
+#pragma unroll
+                for (int b = 0; b < NS; ++b) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int be = 0; be < D; ++be) s += H[al][be] * dphi[(size_t)be * NQ * NS + q * NS + b];
+                    v[b] = (AT)s;
+                }
+#pragma unroll
+                for (int a = 0; a < NS; ++a) {
+                    const AT da = (AT)dphi[(size_t)al * NQ * NS + q * NS + a];
+#pragma unroll
+                    for (int b = 0; b < NS; ++b) acc[a][b] += da * v[b];
+                }
+            }
+        }
+        const AT ad = (AT)g.adet;
+        AT* o = reinterpret_cast<AT*>(A.out) + cell * (int64_t)N * N;
+#pragma unroll
+        for (int a = 0; a < NS; ++a)
+#pragma unroll
+            for (int b = 0; b < NS; ++b) {
+                const AT x = ad * acc[a][b];
+                o[(c1 * NS + a) * N + c2 * NS + b] = x;
+                if (c1 != c2) o[(c2 * NS + b) * N + c1 * NS + a] = x;
+            }
+    }
+}
+
+}  // namespace dev
+
+// ---------------------------------------------------------------- host side
+
+static std::mutex g_svk_mu;
+static std::map<std::tuple<int, int, int, int>, void*> g_svk_tabs;  // (dev, dim, p, q)
+
+static coffee_status svk_table(int dev, int dim, int p, int q, const double** out) {
+    std::lock_guard<std::mutex> lk(g_svk_mu);
+    auto key = std::make_tuple(dev, dim, p, q);
+    auto it = g_svk_tabs.find(key);
+    if (it != g_svk_tabs.end()) {
+        *out = (const double*)it->second;
+        return COFFEE_OK;
+    }
+    Tables t;
+    if (!t.init(dim, p, q)) return COFFEE_E_INVALID_ARG;
+    std::vector<double> h;
+    for (int k = 0; k < t.nq; ++k) h.push_back((double)t.W[k]);
+    for (size_t i = 0; i < t.dphi.size(); ++i) h.push_back((double)t.dphi[i]);
+    void* d = nullptr;
+    if (hipMalloc(&d, h.size() * sizeof(double)) != hipSuccess) return COFFEE_E_NOMEM;
+    if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return COFFEE_E_HIP;
+    }
+    g_svk_tabs[key] = d;
+    *out = (const double*)d;
+    return COFFEE_OK;
+}
+
+void free_svk_tables() {
+    std::lock_guard<std::mutex> lk(g_svk_mu);
+    for (auto& kv : g_svk_tabs) {
+        (void)hipSetDevice(std::get<0>(kv.first));
+        (void)hipFree(kv.second);
+    }
+    g_svk_tabs.clear();
+}
+
+namespace {
+
+// compiled set: triangles and tetrahedra, P1 (q = 2) and P2 (q = 4)
+template <int D, int P, int NQ>
+hipError_t launch_svk(int form, int precision, const dev::SvkArgs& a, hipStream_t s, int ncu, bool reverse) {
+    const int64_t blocks = (a.ncells + 255) / 256;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)ncu * 8));
+    if (reverse) {
+        hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 2, double>), dim3(grid), dim3(256), 0, s, a);
+        if (a.grad_u) hipLaunchKernelGGL((dev::k_svk_residual_scatter<D, P, NQ>), dim3(grid), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    const bool f64 = precision == COFFEE_FP64;
+    if (form == COFFEE_SVK_ENERGY) {
+        if (f64) hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 0, double>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 0, float>), dim3(grid), dim3(256), 0, s, a);
+    } else if (form == COFFEE_SVK_RESIDUAL) {
+        if (f64) hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 1, double>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 1, float>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        constexpr int NB = D * (D + 1) / 2;
+        constexpr int CPW = 64 / NB;
+        const int64_t waves = (a.ncells + CPW - 1) / CPW;
+        const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, (int64_t)ncu * 16));
+        if (f64) hipLaunchKernelGGL((dev::k_svk_jacobian<D, P, NQ, double>), dim3(g2), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((dev::k_svk_jacobian<D, P, NQ, float>), dim3(g2), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t dispatch_svk(int form, int dim, int p, int q, int precision, const dev::SvkArgs& a, hipStream_t s,
+                        int ncu, bool reverse, bool* found) {
+    *found = true;
+    if (dim == 2 && p == 1 && q == 2) return launch_svk<2, 1, 4>(form, precision, a, s, ncu, reverse);
+    if (dim == 2 && p == 2 && q == 4) return launch_svk<2, 2, 9>(form, precision, a, s, ncu, reverse);
+    if (dim == 3 && p == 1 && q == 2) return launch_svk<3, 1, 8>(form, precision, a, s, ncu, reverse);
+    if (dim == 3 && p == 2 && q == 4) return launch_svk<3, 2, 27>(form, precision, a, s, ncu, reverse);
+    *found = false;
+    return hipSuccess;
+}
+
+coffee_status svk_common(int cell, int degree, int q, const double* coords, const int32_t* c2v, int64_t ncells,
+                         const coffee_field* coeffs, const double* constants, int nconst, dev::SvkArgs& a,
+                         const double** tab, int* dev_out) {
+    if (coeffs[0].degree != degree) return COFFEE_E_UNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return COFFEE_E_HIP;
+    coffee_status st = svk_table(dev, cell, degree, q, tab);
+    if (st != COFFEE_OK) return st;
+    std::memset(&a, 0, sizeof a);
+    a.coords = coords;
+    a.c2v = c2v;
+    a.ncells = ncells;
+    a.u = dev::FieldArg{coeffs[0].values, coeffs[0].cell_to_dof};
+    a.mu = nconst > 0 ? constants[0] : 1.0;
+    a.lambda = nconst > 1 ? constants[1] : 1.0;
+    a.tab = *tab;
+    *dev_out = dev;
+    return COFFEE_OK;
+}
+
+}  // namespace
+
+coffee_status assemble_svk(int form, int cell, int degree, int q, int precision, const double* coords, int64_t nvert,
+                           const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, const double* constants,
+                           int nconst, void* out, void* hip_stream) {
+    (void)nvert;
+    if (precision == COFFEE_BF16X3) return COFFEE_E_UNSUPPORTED;
+    if (ncells == 0) return COFFEE_OK;
+    dev::SvkArgs a;
+    const double* tab = nullptr;
+    int dev = 0;
+    coffee_status st = svk_common(cell, degree, q, coords, c2v, ncells, coeffs, constants, nconst, a, &tab, &dev);
+    if (st != COFFEE_OK) return st;
+    a.out = out;
+    bool found = false;
+    hipError_t e = dispatch_svk(form, cell, degree, q, precision, a, (hipStream_t)hip_stream, num_cu(dev), false, &found);
+    if (!found) return COFFEE_E_UNSUPPORTED;
+    return e == hipSuccess ? COFFEE_OK : COFFEE_E_HIP;
+}
+
+coffee_status adjoint_svk_energy(int cell, int degree, int q, const double* coords, const int32_t* c2v, int64_t ncells,
+                                 const coffee_field* coeffs, const double* constants, int nconst, double seed,
+                                 double* grad_coords, double* const* grad_coeff_values, double* cell_value,
+                                 void* hip_stream) {
+    if (ncells > 0 && !grad_coords) return COFFEE_E_INVALID_ARG;
+    if (ncells == 0) return COFFEE_OK;
+    dev::SvkArgs a;
+    const double* tab = nullptr;
+    int dev = 0;
+    coffee_status st = svk_common(cell, degree, q, coords, c2v, ncells, coeffs, constants, nconst, a, &tab, &dev);
+    if (st != COFFEE_OK) return st;
+    a.seed = seed;
+    a.grad_coords = grad_coords;
+    a.grad_u = grad_coeff_values ? grad_coeff_values[0] : nullptr;
+    a.cell_value = cell_value;
+    bool found = false;
+    hipError_t e = dispatch_svk(COFFEE_SVK_ENERGY, cell, degree, q, COFFEE_FP64, a, (hipStream_t)hip_stream,
+                                num_cu(dev), true, &found);
+    if (!found) return COFFEE_E_UNSUPPORTED;
+    return e == hipSuccess ? COFFEE_OK : COFFEE_E_HIP;
 }
 
 }  // namespace coffee
@@ -27,6 +598,9 @@ extern "C" coffee_status coffee_assemble_adjoint(int form, int cell, int degree,
     if (deterministic) return COFFEE_E_UNSUPPORTED;
     (void)workspace;
     (void)workspace_bytes;
+    if (form == COFFEE_SVK_ENERGY)
+        return adjoint_svk_energy(cell, degree, q, coords, c2v, ncells, coeffs, constants, nconst, seed, grad_coords,
+                                  grad_coeff_values, cell_value, hip_stream);
     if (form >= COFFEE_SVK_ENERGY) return COFFEE_E_UNSUPPORTED;
     return adjoint_linear(form, cell, degree, q, fd, coords, nvert, c2v, ncells, coeffs, ncoeff, constants, nconst,
                           lam, u, seed, grad_coords, grad_coeff_values, cell_value, hip_stream);
