@@ -151,6 +151,45 @@ coffee_status coffee_assemble_adjoint(int form, int cell, int degree, int quad_d
 int64_t coffee_adjoint_workspace_size(int form, int cell, int degree, int64_t nvert, int64_t ncells,
                                       const coffee_field* coeffs, int ncoeff);
 
+/* One bin of a mixed batch: a form (mass or Helmholtz) on the cells of one mesh
+ * with one degree. coords / cell_to_vertex describe the mesh the bin's cells
+ * index into; coeff is NULL or one P1 coefficient field on that mesh (device
+ * pointers). variant and task_cells are launch choices made by the autotuner:
+ * variant 0 stages 8 element tensors through LDS before storing them, 1
+ * stores them straight from the matrix-core registers; task_cells (64, 128
+ * or 256) is how many of the bin's cells one wave takes from the queue at a
+ * time. task_cells = 0 selects the autotuned pair for this (form, shape,
+ * degree, precision) from the loaded tuning cache, else (variant, 64). */
+typedef struct {
+    int32_t form, cell, degree, quad_degree;
+    const double* coords;
+    int64_t nvert;
+    const int32_t* cell_to_vertex;
+    int64_t ncells_mesh;
+    const coffee_field* coeff;
+    int32_t variant, task_cells;
+} coffee_segment;
+
+/* Mixed persistent batch (the paper's vectorization across cells, section 4,
+ * extended to cells of different shape, degree and form in one launch).
+ * Entry i of the batch is cell cell_of[i] of segment seg_of[i]; its element
+ * tensor is written at out + out_offset[i] (elements, FP64 or FP32 by
+ * precision; FP32 and FP64 supported). The entries are binned on the device
+ * (histogram, prefix sum, scatter into per-bin lists in the workspace), then
+ * one persistent kernel drains a queue of bin tasks in segment order (put the
+ * costliest bins first). Up to 16 segments. All arrays are device memory;
+ * workspace must hold coffee_batch_workspace_size(nseg, nentries) bytes.
+ * Errors: COFFEE_E_INVALID_ARG (null pointers, nseg outside 1..16, bad
+ * segment), COFFEE_E_UNSUPPORTED (form/degree outside mass or Helmholtz on
+ * P1-P4 triangles or P1-P3 tetrahedra with a P1 coefficient),
+ * COFFEE_E_BUFFER_TOO_SMALL (workspace), COFFEE_E_HIP. */
+coffee_status coffee_assemble_batch(int precision, const coffee_segment* segs, int nseg, const int32_t* seg_of,
+                                    const int64_t* cell_of, const int64_t* out_offset, int64_t nentries,
+                                    void* out, void* workspace, int64_t workspace_bytes, void* hip_stream);
+
+/* Workspace bytes of coffee_assemble_batch. */
+int64_t coffee_batch_workspace_size(int nseg, int64_t nentries);
+
 /* Checks every cell: writes to *first_bad (device int64) the smallest cell
  * index with det J <= 0 or a non-finite coordinate, or -1 if none.
  * Errors: COFFEE_E_INVALID_ARG. */
@@ -168,6 +207,17 @@ const char* coffee_status_string(int status);
  * persistent, one workgroup per 256 cells for the other forms. Not
  * thread-safe with concurrent assembly calls. */
 void coffee_set_launch_options(int grid_mult);
+
+/* Loads a tuning cache written by the autotuner (paper_1407_0904_amd/tuner.py):
+ * per (form, cell, degree, field degree, precision) grid multipliers for
+ * coffee_assemble, and per batch bin type the store variant and task size
+ * (used when a segment's task_cells is 0). Without this call the file named by
+ * the environment variable COFFEE_TUNE_CACHE is loaded on first use. NULL
+ * clears the cache. Text format: lines "linear form cell degree fd prec
+ * grid_mult" and "batch form cell degree prec variant task_cells ns_per_cell".
+ * Errors: COFFEE_E_INVALID_ARG (unreadable file or malformed line; the
+ * previous cache is kept). */
+coffee_status coffee_load_tuning(const char* path);
 
 /* Frees every per-device table cache. Safe to call more than once. */
 void coffee_shutdown(void);

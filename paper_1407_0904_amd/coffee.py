@@ -33,6 +33,13 @@ class _Field(C.Structure):
                 ("degree", C.c_int32), ("ncomp", C.c_int32)]
 
 
+class _Segment(C.Structure):
+    _fields_ = [("form", C.c_int32), ("cell", C.c_int32), ("degree", C.c_int32), ("quad_degree", C.c_int32),
+                ("coords", C.c_void_p), ("nvert", C.c_int64), ("cell_to_vertex", C.c_void_p),
+                ("ncells_mesh", C.c_int64), ("coeff", C.c_void_p), ("variant", C.c_int32),
+                ("task_cells", C.c_int32)]
+
+
 def _load():
     if not os.path.exists(_SO):
         raise ImportError(f"{_SO} is not built: run paper_1407_0904_amd.build.build() first")
@@ -55,6 +62,12 @@ def _load():
     L.coffee_status_string.restype = C.c_char_p
     L.coffee_shutdown.argtypes = []
     L.coffee_shutdown.restype = None
+    L.coffee_assemble_batch.argtypes = [i32, vp, i32, vp, vp, vp, i64, vp, vp, i64, vp]
+    L.coffee_assemble_batch.restype = i32
+    L.coffee_batch_workspace_size.argtypes = [i32, i64]
+    L.coffee_batch_workspace_size.restype = i64
+    L.coffee_load_tuning.argtypes = [C.c_char_p]
+    L.coffee_load_tuning.restype = i32
     L.coffee_set_launch_options.argtypes = [i32]
     L.coffee_set_launch_options.restype = None
     return L
@@ -197,6 +210,54 @@ def coffee_assemble_adjoint(form, cell, degree: int, coords, cell_to_vertex, coe
     return grad_coords, grad_coeffs
 
 
+@dataclass
+class Segment:
+    """One bin of a mixed batch (see coffee_segment in coffee.h)."""
+    form: str
+    cell: int
+    degree: int
+    coords: torch.Tensor
+    cell_to_vertex: torch.Tensor
+    coeff: DeviceField
+    quad_degree: int = -1
+    variant: int = 0
+    task_cells: int = 0
+
+
+def coffee_batch_workspace_size(nseg: int, nentries: int) -> int:
+    return int(_lib.coffee_batch_workspace_size(int(nseg), int(nentries)))
+
+
+def coffee_assemble_batch(segments, seg_of: torch.Tensor, cell_of: torch.Tensor, out_offset: torch.Tensor,
+                          total_elems: int, precision: str = "fp32", out: torch.Tensor | None = None,
+                          workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Packed element tensors of a mixed batch (coffee_assemble_batch)."""
+    odt = torch.float64 if precision == "fp64" else torch.float32
+    dev = seg_of.device
+    n = seg_of.shape[0]
+    if out is None:
+        out = torch.empty(total_elems, dtype=odt, device=dev)
+    if workspace is None:
+        workspace = torch.empty(coffee_batch_workspace_size(len(segments), n), dtype=torch.uint8, device=dev)
+    segs = (_Segment * len(segments))()
+    fields = (_Field * len(segments))()
+    for i, sg in enumerate(segments):
+        f = sg.coeff
+        fields[i] = _Field(_dptr(f.values, torch.float64, "coeff.values"),
+                           _dptr(f.cell_to_dof, torch.int32, "coeff.cell_to_dof", allow_none=True),
+                           int(f.degree), int(f.ncomp))
+        segs[i] = _Segment(FORMS[sg.form], CELLS[sg.cell], int(sg.degree), int(sg.quad_degree),
+                           _dptr(sg.coords, torch.float64, "coords"), sg.coords.shape[0],
+                           _dptr(sg.cell_to_vertex, torch.int32, "cell_to_vertex"), sg.cell_to_vertex.shape[0],
+                           C.addressof(fields[i]), int(sg.variant), int(sg.task_cells))
+    st = _lib.coffee_assemble_batch(PRECISIONS[precision], segs, len(segments),
+                                    _dptr(seg_of, torch.int32, "seg_of"), _dptr(cell_of, torch.int64, "cell_of"),
+                                    _dptr(out_offset, torch.int64, "out_offset"), n, _dptr(out, odt, "out"),
+                                    workspace.data_ptr(), workspace.numel(), _stream(stream))
+    _check(st, "coffee_assemble_batch")
+    return out
+
+
 def coffee_check_geometry(cell, coords, cell_to_vertex, stream=None) -> int:
     """Smallest bad cell index (det J <= 0 or non-finite), or -1."""
     fb = torch.empty(1, dtype=torch.int64, device=coords.device)
@@ -209,6 +270,10 @@ def coffee_check_geometry(cell, coords, cell_to_vertex, stream=None) -> int:
 
 def coffee_set_launch_options(grid_mult: int = 0):
     _lib.coffee_set_launch_options(int(grid_mult))
+
+
+def coffee_load_tuning(path: str | None):
+    _check(_lib.coffee_load_tuning(None if path is None else path.encode()), "coffee_load_tuning")
 
 
 def coffee_shutdown():

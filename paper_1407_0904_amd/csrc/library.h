@@ -24,6 +24,10 @@ coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, cons
                              double seed, double* grad_coords, double* const* grad_coeff_values,
                              double* cell_value, void* hip_stream);
 void free_adjoint_tables();
+coffee_status get_rtable_public(int dev, int form, int dim, int p, int q, int fd, int prec, const void** out);
+int batch_grid_mult();
+int tuned_grid_mult(int form, int cell, int degree, int fd, int prec);
+bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* task_cells);
 void free_svk_tables();
 int num_cu(int dev);
 int blocks_per_cu(int dev, const void* kernel);

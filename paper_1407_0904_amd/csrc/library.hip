@@ -160,6 +160,10 @@ static coffee_status get_rtable(int dev, int form, int dim, int p, int q, int fd
     return COFFEE_OK;
 }
 
+coffee_status get_rtable_public(int dev, int form, int dim, int p, int q, int fd, int prec, const void** out) {
+    return get_rtable(dev, form, dim, p, q, fd, prec, out);
+}
+
 int blocks_per_cu(int dev, const void* kernel) {
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceCtx& c = device_ctx(dev);
@@ -181,6 +185,8 @@ int num_cu(int dev) {
 // default: the pipelined symmetric engine is persistent (a few resident waves of
 // workgroups), the block engine takes one workgroup per 256-cell chunk.
 static int t_grid_mult = 0;
+
+int batch_grid_mult() { return t_grid_mult; }
 
 int grid_for(int dev, const void* kernel, int64_t nchunks, int default_mult) {
     const int cus = num_cu(dev);
@@ -309,7 +315,8 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     a.rfrag = rf;
     a.out = out;
     a.nchunks = (ncells + 255) / 256;
-    const int grid = grid_for(dev, e->kernel, a.nchunks, uses_scalar_engine(form) ? 1 : 64);
+    const int tuned = tuned_grid_mult(form, cell, degree, fd, precision);
+    const int grid = grid_for(dev, e->kernel, a.nchunks, tuned > 0 ? tuned : (uses_scalar_engine(form) ? 1 : 64));
     if (e->launch(a, (hipStream_t)hip_stream, grid) != hipSuccess) return COFFEE_E_HIP;
     return COFFEE_OK;
 }

@@ -1,0 +1,113 @@
+// Tuning cache of libcoffee: launch choices measured by the autotuner
+// (paper_1407_0904_amd/tuner.py), one entry per line of a text file:
+//
+//   linear <form> <cell> <degree> <field_degree> <precision> <grid_mult>
+//   batch  <form> <cell> <degree> <precision> <variant> <task_cells> <ns_per_cell>
+//
+// '#' starts a comment. The paper weighs a cost model against auto-tuning and
+// compares with the best of all feasible factors (section 4, cost model;
+// section 5, op-vect results); here the search is exhaustive over a small
+// space and runs offline, so its cost never lands on the assembly path.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "../../include/coffee.h"
+
+namespace coffee {
+
+struct BatchTune {
+    int variant = 0, task_cells = 0;
+    double ns_per_cell = 0.0;
+};
+
+static std::mutex g_tmu;
+static bool g_loaded = false;
+static std::map<std::tuple<int, int, int, int, int>, int> g_linear;      // -> grid_mult
+static std::map<std::tuple<int, int, int, int>, BatchTune> g_batch;       // (form, cell, degree, prec)
+
+static coffee_status parse(const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return COFFEE_E_INVALID_ARG;
+    std::map<std::tuple<int, int, int, int, int>, int> lin;
+    std::map<std::tuple<int, int, int, int>, BatchTune> bat;
+    char line[512];
+    coffee_status st = COFFEE_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        char* hash = std::strchr(line, '#');
+        if (hash) *hash = '\0';
+        char kind[32];
+        if (std::sscanf(line, "%31s", kind) != 1) continue;
+        if (!std::strcmp(kind, "linear")) {
+            int form, cell, deg, fd, prec, gm;
+            if (std::sscanf(line, "%*s %d %d %d %d %d %d", &form, &cell, &deg, &fd, &prec, &gm) != 6 || gm < 1) {
+                st = COFFEE_E_INVALID_ARG;
+                break;
+            }
+            lin[std::make_tuple(form, cell, deg, fd, prec)] = gm;
+        } else if (!std::strcmp(kind, "batch")) {
+            int form, cell, deg, prec, var, tc;
+            double ns;
+            if (std::sscanf(line, "%*s %d %d %d %d %d %d %lf", &form, &cell, &deg, &prec, &var, &tc, &ns) != 7 ||
+                var < 0 || var > 1 || (tc != 64 && tc != 128 && tc != 256)) {
+                st = COFFEE_E_INVALID_ARG;
+                break;
+            }
+            BatchTune t;
+            t.variant = var;
+            t.task_cells = tc;
+            t.ns_per_cell = ns;
+            bat[std::make_tuple(form, cell, deg, prec)] = t;
+        } else {
+            st = COFFEE_E_INVALID_ARG;
+            break;
+        }
+    }
+    std::fclose(f);
+    if (st == COFFEE_OK) {
+        g_linear.swap(lin);
+        g_batch.swap(bat);
+    }
+    return st;
+}
+
+static void ensure_loaded() {
+    if (g_loaded) return;
+    g_loaded = true;
+    const char* env = std::getenv("COFFEE_TUNE_CACHE");
+    if (env && *env) (void)parse(env);
+}
+
+int tuned_grid_mult(int form, int cell, int degree, int fd, int prec) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    ensure_loaded();
+    auto it = g_linear.find(std::make_tuple(form, cell, degree, fd, prec));
+    return it == g_linear.end() ? 0 : it->second;
+}
+
+bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* task_cells) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    ensure_loaded();
+    auto it = g_batch.find(std::make_tuple(form, cell, degree, prec));
+    if (it == g_batch.end()) return false;
+    *variant = it->second.variant;
+    *task_cells = it->second.task_cells;
+    return true;
+}
+
+}  // namespace coffee
+
+extern "C" coffee_status coffee_load_tuning(const char* path) {
+    std::lock_guard<std::mutex> lk(coffee::g_tmu);
+    coffee::g_loaded = true;
+    if (!path) {
+        coffee::g_linear.clear();
+        coffee::g_batch.clear();
+        return COFFEE_OK;
+    }
+    return coffee::parse(path);
+}

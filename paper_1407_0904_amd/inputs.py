@@ -280,3 +280,75 @@ def random_cells(d: int, ncells: int, rng: np.random.Generator, scale: float = 1
     coords = verts.reshape(-1, d)
     cells = np.arange(ncells * (d + 1), dtype=np.int32).reshape(ncells, d + 1)
     return Mesh(d=d, n=0, coords=np.ascontiguousarray(coords), cells=cells)
+
+
+@dataclass
+class MixedBatch:
+    """Cells of mixed shape, degree and form in one random order.
+
+    segments: list of (form, d, degree) bin types; seg_of[i], cell_of[i]: the
+    bin and the cell (in that shape's mesh) of batch entry i; out_offset[i]:
+    element offset of entry i's tensor in the packed output (batch order).
+    """
+    tri: Mesh
+    tet: Mesh
+    f_tri: Field
+    f_tet: Field
+    segments: list
+    seg_of: np.ndarray
+    cell_of: np.ndarray
+    out_offset: np.ndarray
+    total_elems: int
+
+
+def mixed_batch(n_tri: int = 1000, n_tet: int = 56, tri_counts=(800_000, 600_000, 400_000, 200_000),
+                tet_counts=(500_000, 300_000, 200_000), seed: int = 1) -> MixedBatch:
+    """Triangles P1-P4 drawn from an n_tri^2 x 2 mesh (every cell used once when
+    the counts sum to the mesh size) and tetrahedra P1-P3 drawn without
+    replacement from an n_tet^3 x 6 mesh; Mass and Helmholtz 50/50; f a P1
+    field ~ U[0.5, 1.5] on each mesh; quadrature degree 2p; all entries
+    interleaved in one random order. One PCG64 generator (seed) draws, in
+    order: triangle jitter (20%), tetrahedron jitter (10%), f on triangles,
+    f on tetrahedra, triangle degree assignment, tetrahedron subset and
+    degrees, forms, the interleaving permutation."""
+    rng = np.random.default_rng(seed)
+    tri = make_mesh(2, n_tri, 0.20, rng)
+    tet = make_mesh(3, n_tet, 0.10, rng)
+    f_tri = Field(rng.uniform(0.5, 1.5, size=(tri.nvert, 1)), tri.cells, 1, 1)
+    f_tet = Field(rng.uniform(0.5, 1.5, size=(tet.nvert, 1)), tet.cells, 1, 1)
+    ntri = int(sum(tri_counts))
+    ntet = int(sum(tet_counts))
+    if ntri > tri.ncells or ntet > tet.ncells:
+        raise ValueError("more cells requested than the meshes hold")
+    tri_cells = rng.permutation(tri.ncells)[:ntri]
+    tet_cells = rng.permutation(tet.ncells)[:ntet]
+    segments = []
+    seg_parts, cell_parts = [], []
+    forms = ("mass", "helmholtz")
+    start = 0
+    for p, cnt in enumerate(tri_counts, start=1):
+        cells = tri_cells[start:start + cnt]
+        start += cnt
+        fsel = rng.integers(0, 2, size=cnt)
+        for fi, fname in enumerate(forms):
+            segments.append((fname, 2, p))
+            seg_parts.append(np.full(int((fsel == fi).sum()), len(segments) - 1, dtype=np.int32))
+            cell_parts.append(np.sort(cells[fsel == fi]))
+    start = 0
+    for p, cnt in enumerate(tet_counts, start=1):
+        cells = tet_cells[start:start + cnt]
+        start += cnt
+        fsel = rng.integers(0, 2, size=cnt)
+        for fi, fname in enumerate(forms):
+            segments.append((fname, 3, p))
+            seg_parts.append(np.full(int((fsel == fi).sum()), len(segments) - 1, dtype=np.int32))
+            cell_parts.append(np.sort(cells[fsel == fi]))
+    seg_of = np.concatenate(seg_parts)
+    cell_of = np.concatenate(cell_parts).astype(np.int64)
+    perm = rng.permutation(seg_of.shape[0])
+    seg_of = np.ascontiguousarray(seg_of[perm])
+    cell_of = np.ascontiguousarray(cell_of[perm])
+    sizes = np.array([n_scalar_dofs(d, p) ** 2 for (_, d, p) in segments], dtype=np.int64)[seg_of]
+    out_offset = np.zeros(seg_of.shape[0], dtype=np.int64)
+    np.cumsum(sizes[:-1], out=out_offset[1:])
+    return MixedBatch(tri, tet, f_tri, f_tet, segments, seg_of, cell_of, out_offset, int(sizes.sum()))

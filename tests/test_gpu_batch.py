@@ -1,0 +1,131 @@
+"""GPU mixed persistent batch (coffee_assemble_batch): equal to per-bin
+launches bit for bit, equal to the oracle within the precision's bar."""
+import numpy as np
+import pytest
+
+from paper_1407_0904_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a device"
+    from paper_1407_0904_amd import coffee
+    return coffee
+
+
+def device_batch(cf, mb, variant=0, task_cells=0, order=None):
+    import torch
+    dev = torch.device("cuda:0")
+    tri_c = torch.as_tensor(mb.tri.coords, device=dev)
+    tri_v = torch.as_tensor(mb.tri.cells, device=dev)
+    tet_c = torch.as_tensor(mb.tet.coords, device=dev)
+    tet_v = torch.as_tensor(mb.tet.cells, device=dev)
+    f_tri = cf.DeviceField.from_host(mb.f_tri, dev)
+    f_tet = cf.DeviceField.from_host(mb.f_tet, dev)
+    segs = []
+    for (form, d, p) in mb.segments:
+        c, v, f = (tri_c, tri_v, f_tri) if d == 2 else (tet_c, tet_v, f_tet)
+        vv = variant[len(segs)] if isinstance(variant, (list, tuple)) else variant
+        segs.append(cf.Segment(form, d, p, c, v, f, variant=vv, task_cells=task_cells))
+    arrays = (torch.as_tensor(mb.seg_of, device=dev), torch.as_tensor(mb.cell_of, device=dev),
+              torch.as_tensor(mb.out_offset, device=dev))
+    return segs, arrays
+
+
+def per_bin_reference(cf, mb, segs, precision):
+    """Per-bin coffee_assemble launches, scattered into batch order on the host."""
+    import torch
+    out = np.zeros(mb.total_elems, dtype=np.float64 if precision == "fp64" else np.float32)
+    for b, (form, d, p) in enumerate(mb.segments):
+        idx = np.nonzero(mb.seg_of == b)[0]
+        if idx.size == 0:
+            continue
+        sg = segs[b]
+        cells = torch.as_tensor(mb.cell_of[idx], device=sg.coords.device)
+        sub_c2v = sg.cell_to_vertex[cells].contiguous()
+        sub_f = cf.DeviceField(sg.coeff.values, sg.coeff.cell_to_dof[cells].contiguous(), 1, 1)
+        A = cf.coffee_assemble(form, d, p, sg.coords, sub_c2v, coeffs=[sub_f], precision=precision)
+        A = A.reshape(idx.size, -1).cpu().numpy()
+        nn = A.shape[1]
+        for k, i in enumerate(idx):
+            o = mb.out_offset[i]
+            out[o:o + nn] = A[k]
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("variant,task_cells", [(0, 64), (1, 64), (0, 256), (1, 128)])
+def test_batch_equals_per_bin_launches(cf, precision, variant, task_cells):
+    import torch
+    mb = I.mixed_batch(n_tri=24, n_tet=6, tri_counts=(400, 300, 200, 100), tet_counts=(500, 300, 200), seed=7)
+    segs, (seg_of, cell_of, offs) = device_batch(cf, mb, variant, task_cells)
+    got = cf.coffee_assemble_batch(segs, seg_of, cell_of, offs, mb.total_elems, precision=precision)
+    torch.cuda.synchronize()
+    ref = per_bin_reference(cf, mb, segs, precision)
+    np.testing.assert_array_equal(got.cpu().numpy(), ref)
+
+
+def test_batch_vs_oracle(cf, oracle):
+    import torch
+    from gpu_util import TOL
+    mb = I.mixed_batch(n_tri=16, n_tet=4, tri_counts=(200, 150, 100, 50), tet_counts=(150, 100, 80), seed=3)
+    segs, (seg_of, cell_of, offs) = device_batch(cf, mb, variant=[b % 2 for b in range(14)], task_cells=128)
+    got = cf.coffee_assemble_batch(segs, seg_of, cell_of, offs, mb.total_elems, precision="fp32").cpu().numpy()
+    worst = 0.0
+    for b, (form, d, p) in enumerate(mb.segments):
+        idx = np.nonzero(mb.seg_of == b)[0]
+        mesh, f = (mb.tri, mb.f_tri) if d == 2 else (mb.tet, mb.f_tet)
+        ref = oracle.assemble(form, mesh, p, fields=[f], cells=mb.cell_of[idx])
+        nn = ref.shape[1] * ref.shape[2]
+        g = np.stack([got[mb.out_offset[i]:mb.out_offset[i] + nn] for i in idx]).astype(np.float64)
+        r = ref.reshape(len(idx), -1)
+        err = np.max(np.max(np.abs(g - r), 1) / np.max(np.abs(r), 1))
+        worst = max(worst, err)
+    print(f"batch vs oracle worst cell rel err {worst:.3e}")
+    assert worst < TOL["fp32"]
+
+
+def test_batch_full_size_sampled(cf):
+    """The 3,000,000-entry mixed batch: sampled entries equal per-bin launches bit for bit."""
+    import torch
+    mb = I.mixed_batch()
+    segs, (seg_of, cell_of, offs) = device_batch(cf, mb)
+    got = cf.coffee_assemble_batch(segs, seg_of, cell_of, offs, mb.total_elems, precision="fp32")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for b, (form, d, p) in enumerate(mb.segments):
+        idx = np.nonzero(mb.seg_of == b)[0]
+        pick = np.sort(rng.choice(idx, size=min(200, idx.size), replace=False))
+        sg = segs[b]
+        cells = torch.as_tensor(mb.cell_of[pick], device=sg.coords.device)
+        sub_f = cf.DeviceField(sg.coeff.values, sg.coeff.cell_to_dof[cells].contiguous(), 1, 1)
+        A = cf.coffee_assemble(form, d, p, sg.coords, sg.cell_to_vertex[cells].contiguous(), coeffs=[sub_f],
+                               precision="fp32").reshape(len(pick), -1)
+        nn = A.shape[1]
+        gidx = torch.as_tensor((mb.out_offset[pick][:, None] + np.arange(nn)[None, :]).reshape(-1), device=got.device)
+        np.testing.assert_array_equal(got[gidx].reshape(len(pick), nn).cpu().numpy(), A.cpu().numpy())
+
+
+def test_batch_validation(cf):
+    import torch
+    mb = I.mixed_batch(n_tri=4, n_tet=2, tri_counts=(4, 4, 4, 4), tet_counts=(4, 4, 4), seed=2)
+    segs, (seg_of, cell_of, offs) = device_batch(cf, mb)
+    with pytest.raises(cf.CoffeeError) as ei:
+        cf.coffee_assemble_batch(segs[:0], seg_of, cell_of, offs, mb.total_elems)
+    assert ei.value.code == 1
+    bad = list(segs)
+    bad[0] = cf.Segment("elasticity", 2, 1, segs[0].coords, segs[0].cell_to_vertex, segs[0].coeff)
+    with pytest.raises(cf.CoffeeError) as ei:
+        cf.coffee_assemble_batch(bad, seg_of, cell_of, offs, mb.total_elems)
+    assert ei.value.code == 2
+    bad[0] = cf.Segment("mass", 2, 1, segs[0].coords, segs[0].cell_to_vertex, segs[0].coeff, task_cells=100)
+    with pytest.raises(cf.CoffeeError) as ei:
+        cf.coffee_assemble_batch(bad, seg_of, cell_of, offs, mb.total_elems)
+    assert ei.value.code == 1
+    small = torch.empty(16, dtype=torch.uint8, device=seg_of.device)
+    with pytest.raises(cf.CoffeeError) as ei:
+        cf.coffee_assemble_batch(segs, seg_of, cell_of, offs, mb.total_elems, workspace=small)
+    assert ei.value.code == 3
