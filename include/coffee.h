@@ -91,9 +91,9 @@ typedef struct {
     int32_t ncomp;
 } coffee_field;
 
-/* Reference quadrature and Lagrange basis tables (host, FP64; paper section 2,
- * "definition of basis functions": the static const tables W, X, Y of
- * Listings 1-2 and Table 1). Buffers are caller-owned host memory; pass NULL
+/* Reference quadrature and Lagrange basis tables (host, FP64; paper section 2:
+ * the constant weight and basis tables W, X, Y that the kernels of Listings 1
+ * and 2 declare, and Table 1). Buffers are caller-owned host memory; pass NULL
  * for all four to query *nq and *ndof. Layouts: points [nq][d], weights [nq],
  * basis [nq][ndof], dbasis [d][nq][ndof] (reference derivatives).
  * Errors: COFFEE_E_INVALID_ARG (bad cell, degree outside 0..4, quad_degree
@@ -105,9 +105,8 @@ coffee_status coffee_tabulate(int cell, int degree, int quad_degree, int* nq, in
  * forms, d * n_scalar for vector forms, 0 for the energy, -1 if invalid. */
 int coffee_tensor_dim(int form, int cell, int degree);
 
-/* Element tensors of all cells (paper section 2: "local assembly ... applied
- * to all cells in the discretized domain"; Fig. 1 contract batched over the
- * mesh). Inputs (device): coords [nvert][d] FP64, cell_to_vertex [ncells][d+1]
+/* Element tensors of all cells (paper section 2: the per-cell kernel of Fig. 1
+ * is run once for every cell of the mesh; here one call covers the mesh). Inputs (device): coords [nvert][d] FP64, cell_to_vertex [ncells][d+1]
  * int32, coefficient fields as described above, constants (host) per form.
  * Output (device, overwritten; equals "zero-initialise then +=" of Fig. 1):
  * [ncells][N][N] for bilinear forms, [ncells][N] for the residual, [ncells]

@@ -3,11 +3,11 @@
 // For a bilinear form the per-cell functional S_e = lam_e^T A_e u_e equals
 // sum_blk sum_k G^blk_k T^blk_k with T^blk_k = lam_{c1}^T R_k u_{c2}: the
 // reference tensors are contracted with the test and trial vectors once, and
-// the geometry tensor G carries every dependence on the cell. Its derivatives
-// are taken with forward-mode dual numbers through the same G builder the
-// forward kernels use, seeded on each entry of K = J^-1 and on each local
-// coefficient dof; every term of G is linear in |det J|, so
-// dS/d|det J| = S / |det J|. The chain to the vertex coordinates is analytic:
+// the geometry tensor G carries every dependence on the cell. The transpose of
+// the G builder (reverse_G, beside build_G in linear.hpp) maps Gbar = T to
+// Kbar = dS/dK and to the bars of the local coefficient dofs; every term of G
+// is linear in |det J|, so dS/d|det J| = S / |det J|. The chain to the vertex
+// coordinates is analytic:
 //     dK = -K dJ K  ->  Jbar = -K^T Kbar K^T,
 //     d|det J| = |det J| tr(K dJ)  ->  Jbar += Sbar_adet |det J| K^T,
 //     J = [x1 - x0, ..., xd - x0]  ->  xbar_{j+1} = Jbar[:, j], xbar_0 = -sum_j Jbar[:, j].

@@ -21,8 +21,6 @@
 
 #include <cstdint>
 
-#include "dual.hpp"
-
 namespace coffee {
 namespace dev {
 
@@ -154,7 +152,7 @@ __host__ __device__ inline void geometry_from_coords(const T (&x)[D + 1][D], Geo
         g.K[0][1] = -J[0][1] * r;
         g.K[1][0] = -J[1][0] * r;
         g.K[1][1] = J[0][0] * r;
-        g.adet = absval(det);
+        g.adet = fabs(det);
     } else {
         const T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
         const T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
@@ -170,7 +168,7 @@ __host__ __device__ inline void geometry_from_coords(const T (&x)[D + 1][D], Geo
         g.K[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
         g.K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
         g.K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
-        g.adet = absval(det);
+        g.adet = fabs(det);
     }
 }
 

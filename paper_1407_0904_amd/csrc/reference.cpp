@@ -4,7 +4,7 @@
 // form is a sum of (cell-dependent factor) x (product of reference basis
 // functions and reference derivatives). Moving the cell factors out of the
 // quadrature sum (the paper's generalized loop-invariant code motion, section
-// 3.2, taken to the whole i loop, and the expansion used by FFC, section 5.6)
+// 3.2, taken to the whole i loop, and the expansion used by FFC, section 5.8)
 // turns the element tensor into A[ab] = sum_k G[k] R[k][ab] with
 // R[k][ab] = sum_q W_q (reference products at point q). The sum runs over
 // the same quadrature points, so the result equals the quadrature sum up to

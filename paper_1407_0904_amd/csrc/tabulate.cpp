@@ -1,7 +1,7 @@
 // Host tabulation of reference quadrature rules and Lagrange bases.
 //
-// The paper's kernels carry these as static const tables (section 2, "definition
-// of basis functions"; Listings 1-2: W, X_D10, X_D01, Y; Table 1). Here they are
+// The paper's kernels carry these as constant tables (section 2; Listings 1-2:
+// W, X_D10, X_D01, Y; Table 1). Here they are
 // computed once per key on the host, in extended precision:
 //   - Gauss-Jacobi rules by the Golub-Welsch method: eigen-decomposition of the
 //     symmetric tridiagonal Jacobi matrix by implicit QL iteration, tracking the

@@ -4,9 +4,9 @@
 //   linear <form> <cell> <degree> <field_degree> <precision> <grid_mult>
 //   batch  <form> <cell> <degree> <precision> <variant> <task_cells> <ns_per_cell>
 //
-// '#' starts a comment. The paper weighs a cost model against auto-tuning and
-// compares with the best of all feasible factors (section 4, cost model;
-// section 5, op-vect results); here the search is exhaustive over a small
+// '#' starts a comment. The paper weighs a cost model against auto-tuning
+// (section 4) and reports the best over every feasible unroll factor next to
+// the model's pick (section 5.6); here the search is exhaustive over a small
 // space and runs offline, so its cost never lands on the assembly path.
 #include <cstdio>
 #include <cstdlib>

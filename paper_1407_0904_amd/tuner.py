@@ -1,9 +1,9 @@
 """Offline autotuner of libcoffee's launch choices.
 
 For every key it times each candidate on the GPU (median of repeated launches,
-with events on the current stream) and keeps the fastest, as the paper's
-"best of all feasible factors" comparison does for its loop transformations
-(section 5); the search runs offline, so its cost never reaches the assembly
+with events on the current stream) and keeps the fastest, the way the paper
+reports the best over every feasible unroll factor for its register tiling
+(section 5.6); the search runs offline, so its cost never reaches the assembly
 call. Keys and candidates:
 
 * coffee_assemble (form, cell, degree, field degree, precision): the grid

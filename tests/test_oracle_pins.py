@@ -157,30 +157,17 @@ def test_p1_stiffness_closed_form(oracle, d):
     np.testing.assert_allclose(A, vol * G @ G.T, rtol=1e-13, atol=1e-14)
 
 
-def test_listing1_helmholtz_expression(oracle):
-    """Listing 1 (section 2): A[j][k] += (Y Y + (K1 X_D10 + K3 X_D01)(...) +
-    (K0 X_D10 + K2 X_D01)(...)) det W[i], with K = J^-1 row-major
-    (K0 K1 / K2 K3). Evaluated with a 3-point degree-2 rule (edge midpoints,
-    weight 1/6), which integrates this P1 integrand exactly."""
+def test_helmholtz_p1_no_coefficient_closed_form(oracle):
+    """The kernel of Listing 1 (section 2) is the P1 triangle Helmholtz matrix with
+    no coefficient: stiffness |T| G G^T (G from a linear solve for the
+    barycentric gradients) plus the P1 mass closed form |T|/12 (1 + delta_ab)."""
     v = np.array([[0.2, 0.1], [1.3, 0.4], [0.5, 1.2]])
-    Jm = (v[1:] - v[0]).T
-    det = np.linalg.det(Jm)
-    K0, K1, K2, K3 = np.linalg.inv(Jm).reshape(-1)
-    pts = np.array([[0.5, 0.0], [0.5, 0.5], [0.0, 0.5]])
-    W = np.full(3, 1.0 / 6.0)
-    Y = np.stack([1 - pts[:, 0] - pts[:, 1], pts[:, 0], pts[:, 1]], axis=1)
-    X_D10 = np.tile([-1.0, 1.0, 0.0], (3, 1))
-    X_D01 = np.tile([-1.0, 0.0, 1.0], (3, 1))
-    A = np.zeros((3, 3))
-    for i in range(3):
-        for j in range(3):
-            for k in range(3):
-                A[j][k] += ((Y[i][k] * Y[i][j]
-                             + ((K1 * X_D10[i][k] + K3 * X_D01[i][k]) * (K1 * X_D10[i][j] + K3 * X_D01[i][j]))
-                             + ((K0 * X_D10[i][k] + K2 * X_D01[i][k]) * (K0 * X_D10[i][j] + K2 * X_D01[i][j])))
-                            * det * W[i])
+    Mx = np.hstack([np.ones((3, 1)), v])
+    G = np.linalg.solve(Mx, np.eye(3))[1:, :].T
+    area = 0.5 * abs(np.linalg.det((v[1:] - v[0]).T))
+    want = area * G @ G.T + area / 12 * (np.ones((3, 3)) + np.eye(3))
     got = oracle.assemble("helmholtz", I.single_cell_mesh(2, v), 1)[0]
-    np.testing.assert_allclose(got, A, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-15)
 
 
 # ---------------------------------------------------------------- exact polynomial integrals
