@@ -37,6 +37,10 @@ HBM_PEAK_GBS = 8000.0
 FLOP_PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
 METRIC = "cells/s + GB/s (frac of roofline) per form; FP32/BF16 vs FP64 at stated err"
 TUNING = os.path.join(ROOT, "paper_1407_0904_amd", "tuning_mi355x.txt")
+# HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by a plain copy of known size (profiles/
+# k_scalar_helmholtz_p2_tet_fp64.md); valid only for the kernel they were taken on.
+TRAFFIC = {("helmholtz_p2_tet", "fp64"): 1421.1e6}
 
 WORKLOADS = {
     "helmholtz_p2_tet": "Helmholtz P2 tetrahedra, 64^3 x 6 cells, f P2 ~ U[0.5,1.5], jitter 10%, q = 4",
@@ -432,7 +436,8 @@ def main():
                    "element_tensor": list(shape[1:]), "precision": args.precision,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": main_r["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": main_r["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": main_r["gbs"] / HBM_PEAK_GBS,
+                     "traffic": TRAFFIC.get((args.workload, args.precision)),
                      "algorithmic_bytes_per_launch": main_r["bytes"], "kernel_ms": main_r["kernel_ms"]},
         "max_cell_rel_err_vs_oracle": main_r["err"],
         "variants": {p: {"cells_per_s": r["cells_per_s"], "ms": r["ms"], "gbs": r["gbs"],

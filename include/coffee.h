@@ -155,10 +155,11 @@ int64_t coffee_adjoint_workspace_size(int form, int cell, int degree, int64_t nv
  * index into; coeff is NULL or one P1 coefficient field on that mesh (device
  * pointers). variant and task_cells are launch choices made by the autotuner:
  * variant 0 stages 8 element tensors through LDS before storing them, 1
- * stores them straight from the matrix-core registers; task_cells (64, 128
- * or 256) is how many of the bin's cells one wave takes from the queue at a
- * time. task_cells = 0 selects the autotuned pair for this (form, shape,
- * degree, precision) from the loaded tuning cache, else (variant, 64). */
+ * stores them straight from the matrix-core registers; task_cells (a
+ * multiple of 64, at most 1024) is how many of the bin's cells one wave takes
+ * from the queue at a time. task_cells = 0 selects the autotuned pair for
+ * this (form, shape, degree, precision) from the loaded tuning cache, else
+ * (variant, 256). The bin's mesh must have at most 2^31 - 1 cells. */
 typedef struct {
     int32_t form, cell, degree, quad_degree;
     const double* coords;
@@ -174,9 +175,11 @@ typedef struct {
  * Entry i of the batch is cell cell_of[i] of segment seg_of[i]; its element
  * tensor is written at out + out_offset[i] (elements, FP64 or FP32 by
  * precision; FP32 and FP64 supported). The entries are binned on the device
- * (histogram, prefix sum, scatter into per-bin lists in the workspace), then
- * one persistent kernel drains a queue of bin tasks in segment order (put the
- * costliest bins first). Up to 16 segments. All arrays are device memory;
+ * (histogram, prefix sum, scatter of each entry's cell index and output offset
+ * into per-bin ranges of the workspace), then one persistent kernel drains a
+ * queue of bin tasks in segment order (put the costliest bins first). Output
+ * regions of different entries must not overlap; cell_of[i] must index a cell
+ * of segment seg_of[i]'s mesh. Up to 16 segments. All arrays are device memory;
  * workspace must hold coffee_batch_workspace_size(nseg, nentries) bytes.
  * Errors: COFFEE_E_INVALID_ARG (null pointers, nseg outside 1..16, bad
  * segment), COFFEE_E_UNSUPPORTED (form/degree outside mass or Helmholtz on

@@ -3,16 +3,18 @@
 // applied to a heterogeneous set of cells).
 //
 // 1. Binning on the device: per-workgroup histograms of the entries' segment
-//    ids, a prefix sum, and a scatter of entry indices into per-bin lists
-//    (each workgroup reserves one contiguous range per bin, so the relative
-//    order of entries inside a workgroup's slice is kept).
+//    ids, a prefix sum, and a scatter of each entry's cell index and output
+//    offset into its bin's contiguous range of the workspace (each workgroup
+//    reserves one range per bin with one atomic).
 // 2. One persistent kernel: every wave takes tasks (task_cells consecutive
-//    entries of one bin) from a single atomic queue that lists the bins in
-//    segment order, and runs the symmetric-form contraction of that bin's
-//    (form, shape, degree) on them: FP64 geometry and G per lane, MFMA
-//    contraction against the bin's reference tensors, element tensors written
-//    to the entries' own output offsets, either staged through LDS (8 tensors
-//    at a time) or stored straight from the accumulators.
+//    binned entries of one bin) from a single atomic queue that lists the bins
+//    in segment order, and runs the symmetric-form engine of that bin's
+//    (form, shape, degree) on them 64 entries at a time, software-pipelined
+//    three deep inside the task (while group g is contracted and stored, the
+//    coordinates and coefficient dofs of group g+1, the vertex indices of
+//    g+2 and the binned cell index and offset of g+3 are in flight). Element
+//    tensors go to the entries' own offsets, either staged through LDS (8
+//    tensors at a time) or stored straight from the accumulators.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,7 +54,8 @@ struct BatchArgs {
     unsigned long long* offs;     // [kMaxBins]
     unsigned long long* cursor;   // [kMaxBins]
     unsigned long long* queue;    // [1]
-    int32_t* list;                // [nentries]
+    int64_t* boff;                // [nentries] output offsets in bin order
+    int32_t* bcell;               // [nentries] cell indices in bin order
 };
 
 // ---------------------------------------------------------------- binning
@@ -79,8 +82,10 @@ __global__ void k_bin_scan(BatchArgs A) {
     }
 }
 
-// Each workgroup takes a contiguous slice of entries, counts per bin, reserves
-// one range per bin and writes its entries in slice order.
+// Each workgroup takes a contiguous slice of entries, counts them per bin,
+// reserves one range per bin and writes every entry's cell index and output
+// offset into it (the order inside a workgroup's range is immaterial: each
+// entry's result depends only on its own data).
 __global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A, int64_t slice) {
     __shared__ unsigned int h[kMaxBins];
     __shared__ unsigned long long base[kMaxBins];
@@ -95,173 +100,211 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A, int64_t slice)
         h[threadIdx.x] = 0;
     }
     __syncthreads();
-    // in-order placement within the slice: one pass per 256 entries, ranks by prefix in LDS
-    __shared__ int seg[256];
-    for (int64_t c = s0; c < s1; c += blockDim.x) {
-        const int64_t i = c + threadIdx.x;
-        const int sg = i < s1 ? A.seg_of[i] : -1;
-        seg[threadIdx.x] = sg;
-        __syncthreads();
-        if (sg >= 0) {
-            int rank = 0;
-            for (int t = 0; t < (int)threadIdx.x; ++t) rank += (seg[t] == sg);
-            A.list[base[sg] + h[sg] + rank] = (int32_t)i;
-        }
-        __syncthreads();
-        if (threadIdx.x < A.nbins) {
-            int cnt = 0;
-            for (int t = 0; t < (int)blockDim.x; ++t) cnt += (seg[t] == (int)threadIdx.x);
-            h[threadIdx.x] += cnt;
-        }
-        __syncthreads();
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        const int sg = A.seg_of[i];
+        const unsigned long long pos = base[sg] + atomicAdd(&h[sg], 1u);
+        A.bcell[pos] = (int32_t)A.cell_of[i];
+        A.boff[pos] = A.out_offset[i];
     }
 }
 
 // ---------------------------------------------------------------- tasks
 
-template <int D, int P, int PREC>
-struct BatchCfg {
-    static constexpr int NS = nsc(D, P);
-    static constexpr int NN = NS * NS;
-};
-
 constexpr int kGtileRow = 16;  // >= any G row of the compiled bin types (KR <= 10)
 
-template <int FORM, int D, int P, int FD, int PREC>
+// Contract one 16-entry tile (rows j of the current group) and store each
+// entry's tensor at its own offset. FULL: all 64 entries of the group exist,
+// so the store count is a compile-time constant.
+template <int FORM, int D, int P, int FD, int PREC, int VARIANT, bool FULL>
+__device__ inline void batch_tile(ScalarWave<FORM, D, P, FD, PREC>& W, const double* Gv, int j, int64_t myoff,
+                                  bool valid, int64_t* soffs) {
+    using C = ScalarCfg<FORM, D, P, FD, PREC>;
+    using acc_t = typename C::acc_t;
+    using out_t = typename C::out_t;
+    constexpr int NS = C::NS, NN = C::NN, NT = C::NT, NU = C::NU, ROW = C::ROW;
+    static_assert(ROW <= kGtileRow, "G row does not fit the batch tile");
+    const int lane = W.lane, col = W.col;
+    if ((lane >> 4) == j) put_G_row<FORM, D, FD, PREC>(W.gtile + col * ROW, Gv);
+    wave_sync();
+    acc_t acc[NT];
+    scalar_contract<FORM, D, P, FD, PREC, NT>(W, 0, acc);
+    if constexpr (VARIANT == 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            wave_sync();
+            if ((lane >> 3) == 2 * j + h) soffs[lane & 7] = (FULL || valid) ? myoff : -1;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (t * 16 + col >= NU) continue;
+                const int oab = W.ua[t] * NS + W.ub[t], oba = W.ub[t] * NS + W.ua[t];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = acc_row<PREC>(lane, v);
+                    if ((row >> 3) != h) continue;
+                    const out_t x = (out_t)acc[t][v];
+                    W.stage[(row & 7) * NN + oab] = x;
+                    W.stage[(row & 7) * NN + oba] = x;
+                }
+            }
+            wave_sync();
+            constexpr int TOT = 8 * NN, IT = (TOT + 63) / 64;
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const int k = i * 64 + lane;
+                if (k < TOT) {
+                    const int c = k / NN, e = k - (k / NN) * NN;
+                    const int64_t o = soffs[c];
+                    if (FULL || o >= 0) W.out[o + e] = W.stage[k];
+                }
+            }
+        }
+    } else {
+        // offsets of the 4 rows this lane holds, fetched with every lane active
+        int64_t roff[4];
+        bool rok[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int src = 16 * j + acc_row<PREC>(lane, v);
+            roff[v] = __shfl(myoff, src);
+            rok[v] = FULL || __shfl((int)valid, src) != 0;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t * 16 + col >= NU) continue;
+            const int a = W.ua[t], bb = W.ub[t];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (rok[v]) {
+                    const out_t x = (out_t)acc[t][v];
+                    W.out[roff[v] + a * NS + bb] = x;
+                    W.out[roff[v] + bb * NS + a] = x;
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// n binned entries first .. first + n - 1 of one bin, 64 per group.
+template <int FORM, int D, int P, int FD, int PREC, int VARIANT>
 __device__ void batch_task(const BatchArgs& A, const BinDesc& bd, int64_t first, int n, int lane,
                            typename PrecT<PREC>::gtype* gtile, typename PrecT<PREC>::otype* stage, int64_t* soffs) {
-    using frag_t = typename PrecT<PREC>::frag;
-    using acc_t = typename PrecT<PREC>::acc;
-    using out_t = typename PrecT<PREC>::otype;
-    constexpr int NS = nsc(D, P), NN = NS * NS;
-    constexpr int KR = kref(FORM, D, FD);
-    constexpr int KS = ksteps(FORM, D, FD, PREC);
-    constexpr int NT = ntiles_sym(D, P);
-    constexpr int NU = nuniq(D, P);
-    constexpr int ROW = GLayout<FORM, D, FD, PREC>::ROW;
-    static_assert(ROW <= kGtileRow, "G row does not fit the batch tile");
-    const int col = lane & 15;
-    const frag_t* rf = reinterpret_cast<const frag_t*>(bd.rfrag);
-    out_t* out = reinterpret_cast<out_t*>(A.out);
+    using C = ScalarCfg<FORM, D, P, FD, PREC>;
+    constexpr int KR = C::KR, NT = C::NT, KS = C::KS, NS = C::NS;
+    ScalarWave<FORM, D, P, FD, PREC> W;
+    W.lane = lane;
+    W.col = lane & 15;
+    W.gtile = gtile;
+    W.stage = stage;
+    W.rf = reinterpret_cast<const typename C::frag_t*>(bd.rfrag);
+    W.out = reinterpret_cast<typename C::out_t*>(A.out);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        int u = t * 16 + W.col, a = 0;
+        while (a < NS - 1 && u >= NS - a) { u -= NS - a; ++a; }
+        W.ua[t] = a;
+        W.ub[t] = a + u;
+    }
+    if constexpr (C::RREG) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) W.rreg[t][s] = W.rf[(t * KS + s) * 64 + lane];
+    }
     LinArgs L;
     L.coords = bd.coords;
     L.c2v = bd.c2v;
     L.f0 = bd.f0;
-    int ua[NT], ub[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        int u = t * 16 + col, a = 0;
-        while (a < NS - 1 && u >= NS - a) { u -= NS - a; ++a; }
-        ua[t] = a;
-        ub[t] = a + u;
+    L.f1 = FieldArg{nullptr, nullptr};
+    const int nfull = n >> 6, ng = (n + 63) >> 6;
+    const int64_t last = first + n - 1;
+    // binned position of this lane's entry in group g (clamped into the task)
+    auto at = [&](int g) -> int64_t {
+        const int gg = g < ng ? g : ng - 1;
+        const int64_t p = first + 64 * (int64_t)gg + lane;
+        return p < last ? p : last;
+    };
+    double Gv[KR];
+    CellIdx<FORM, D, FD> ix;
+    CellRaw<FORM, D, FD> raw;
+    int c1, c2;
+    int64_t o0, o1, o2;
+    {
+        const int64_t p0 = at(0);
+        const int c0 = A.bcell[p0];
+        o0 = A.boff[p0];
+        load_idx<FORM, D, FD>(L, c0, ix);
+        load_raw<FORM, D, FD>(L, c0, ix, raw);
+        G_from_raw<FORM, D, FD>(raw, L, true, Gv);
+        const int64_t p1 = at(1);
+        c1 = A.bcell[p1];
+        o1 = A.boff[p1];
+        load_idx<FORM, D, FD>(L, c1, ix);
+        const int64_t p2 = at(2);
+        c2 = A.bcell[p2];
+        o2 = A.boff[p2];
     }
-#pragma unroll 1
-    for (int g0 = 0; g0 < n; g0 += 64) {
-        const bool valid = g0 + lane < n;
-        const int64_t li = first + g0 + (valid ? lane : 0);
-        const int64_t entry = A.list[li];
-        const int64_t cell = A.cell_of[entry];
-        const int64_t myoff = A.out_offset[entry];
-        double Gv[KR];
-        {
-            CellIdx<FORM, D, FD> ix;
-            CellRaw<FORM, D, FD> raw;
-            load_idx<FORM, D, FD>(L, cell, ix);
-            load_raw<FORM, D, FD>(L, cell, ix, raw);
-            CellData<FORM, D, FD> cd;
-            cell_from_raw<FORM, D, FD>(raw, cd);
-            build_G<FORM, D, FD, 0, 0>(cd, L, Gv);
-        }
+    // Complete the prologue's loads before the first store (one in-order
+    // counter covers loads and stores).
+    if constexpr (C::RREG) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) asm volatile("" ::"v"(W.rreg[t][s]));
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) asm volatile("" ::"v"(Gv[k]));
+#pragma unroll
+    for (int v = 0; v <= D; ++v) asm volatile("" ::"v"(ix.v[v]));
+    asm volatile("" ::"v"(c2), "v"(o1), "v"(o2));
+    for (int g = 0; g < nfull; ++g) {
+        load_raw<FORM, D, FD>(L, c1, ix, raw);  // group g + 1
+        load_idx<FORM, D, FD>(L, c2, ix);       // group g + 2
+        const int64_t p3 = at(g + 3);
+        const int c3 = A.bcell[p3];
+        const int64_t o3 = A.boff[p3];
+        batch_tile<FORM, D, P, FD, PREC, VARIANT, true>(W, Gv, 0, o0, true, soffs);
+        batch_tile<FORM, D, P, FD, PREC, VARIANT, true>(W, Gv, 1, o0, true, soffs);
+        batch_tile<FORM, D, P, FD, PREC, VARIANT, true>(W, Gv, 2, o0, true, soffs);
+        batch_tile<FORM, D, P, FD, PREC, VARIANT, true>(W, Gv, 3, o0, true, soffs);
+        G_from_raw<FORM, D, FD>(raw, L, true, Gv);
+        o0 = o1;
+        o1 = o2;
+        o2 = o3;
+        c1 = c2;
+        c2 = c3;
+    }
+    if (nfull < ng) {
+        // the partial last group (its data came with the pipeline)
+        const int rem = n - 64 * nfull;
+        const bool valid = lane < rem;
 #pragma unroll 1
         for (int j = 0; j < 4; ++j) {
-            if (g0 + 16 * j >= n) break;  // wave-uniform
-            if ((lane >> 4) == j) put_G_row<FORM, D, FD, PREC>(gtile + col * ROW, Gv);
-            wave_sync();
-            constexpr int NTC = NT;
-            acc_t acc[NTC];
-#pragma unroll
-            for (int t = 0; t < NTC; ++t) acc[t] = acc_t{0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const frag_t a = load_afrag<PREC>(gtile, ROW, lane, s);
-#pragma unroll
-                for (int t = 0; t < NTC; ++t) acc[t] = mfma<PREC>(a, rf[(t * KS + s) * 64 + lane], acc[t]);
-            }
-            if (bd.variant == 0) {
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    wave_sync();
-                    // output offsets of the 8 cells of this half
-                    if ((lane >> 3) == 2 * j + h) soffs[lane & 7] = valid ? myoff : -1;
-#pragma unroll
-                    for (int t = 0; t < NTC; ++t) {
-                        if (t * 16 + col >= NU) continue;
-                        const int oab = ua[t] * NS + ub[t], oba = ub[t] * NS + ua[t];
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = acc_row<PREC>(lane, v);
-                            if ((row >> 3) != h) continue;
-                            const out_t x = (out_t)acc[t][v];
-                            stage[(row & 7) * NN + oab] = x;
-                            stage[(row & 7) * NN + oba] = x;
-                        }
-                    }
-                    wave_sync();
-#pragma unroll 2
-                    for (int k = lane; k < 8 * NN; k += 64) {
-                        const int c = k / NN, e = k - (k / NN) * NN;
-                        const int64_t o = soffs[c];
-                        if (o >= 0) out[o + e] = stage[k];
-                    }
-                }
-            } else {
-                // offsets of the 4 rows this lane holds, fetched with every lane active
-                int64_t roff[4];
-                bool rok[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int src = 16 * j + acc_row<PREC>(lane, v);
-                    roff[v] = __shfl(myoff, src);
-                    rok[v] = g0 + src < n;
-                }
-#pragma unroll
-                for (int t = 0; t < NTC; ++t) {
-                    if (t * 16 + col >= NU) continue;
-                    const int a = ua[t], bb = ub[t];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        if (rok[v]) {
-                            const out_t x = (out_t)acc[t][v];
-                            out[roff[v] + a * NS + bb] = x;
-                            out[roff[v] + bb * NS + a] = x;
-                        }
-                    }
-                }
-            }
-            wave_sync();
+            if (16 * j >= rem) break;  // wave-uniform
+            batch_tile<FORM, D, P, FD, PREC, VARIANT, false>(W, Gv, j, o0, valid, soffs);
         }
     }
 }
 
-template <int PREC>
-__device__ inline void batch_dispatch(const BatchArgs& A, const BinDesc& bd, int64_t first, int n, int lane,
-                                      typename PrecT<PREC>::gtype* gtile, typename PrecT<PREC>::otype* stage,
-                                      int64_t* soffs) {
+template <int PREC, int VARIANT>
+__device__ inline void batch_dispatch_v(const BatchArgs& A, const BinDesc& bd, int64_t first, int n, int lane,
+                                        typename PrecT<PREC>::gtype* gtile, typename PrecT<PREC>::otype* stage,
+                                        int64_t* soffs) {
     switch (bd.type) {
-        case 0: batch_task<F_MASS, 2, 1, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 1: batch_task<F_MASS, 2, 2, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 2: batch_task<F_MASS, 2, 3, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 3: batch_task<F_MASS, 2, 4, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 4: batch_task<F_MASS, 3, 1, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 5: batch_task<F_MASS, 3, 2, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 6: batch_task<F_MASS, 3, 3, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 7: batch_task<F_HELM, 2, 1, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 8: batch_task<F_HELM, 2, 2, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 9: batch_task<F_HELM, 2, 3, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 10: batch_task<F_HELM, 2, 4, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 11: batch_task<F_HELM, 3, 1, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 12: batch_task<F_HELM, 3, 2, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
-        case 13: batch_task<F_HELM, 3, 3, 1, PREC>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 0: batch_task<F_MASS, 2, 1, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 1: batch_task<F_MASS, 2, 2, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 2: batch_task<F_MASS, 2, 3, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 3: batch_task<F_MASS, 2, 4, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 4: batch_task<F_MASS, 3, 1, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 5: batch_task<F_MASS, 3, 2, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 6: batch_task<F_MASS, 3, 3, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 7: batch_task<F_HELM, 2, 1, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 8: batch_task<F_HELM, 2, 2, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 9: batch_task<F_HELM, 2, 3, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 10: batch_task<F_HELM, 2, 4, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 11: batch_task<F_HELM, 3, 1, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 12: batch_task<F_HELM, 3, 2, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
+        case 13: batch_task<F_HELM, 3, 3, 1, PREC, VARIANT>(A, bd, first, n, lane, gtile, stage, soffs); break;
         default: break;
     }
 }
@@ -281,14 +324,13 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs A, int stage_elems) {
     int64_t* soffs = reinterpret_cast<int64_t*>(mine + (size_t)16 * kGtileRow * sizeof(g_t));
     out_t* stage = reinterpret_cast<out_t*>(mine + (size_t)16 * kGtileRow * sizeof(g_t) + 8 * sizeof(int64_t));
     // tasks per bin from the device counts
-    int64_t ntask[kMaxBins], tstart[kMaxBins + 1];
+    int64_t tstart[kMaxBins + 1];
     tstart[0] = 0;
 #pragma unroll
     for (int b = 0; b < kMaxBins; ++b) {
         const int64_t c = b < A.nbins ? (int64_t)A.counts[b] : 0;
         const int tc = b < A.nbins ? A.bins[b].task_cells : 64;
-        ntask[b] = (c + tc - 1) / tc;
-        tstart[b + 1] = tstart[b] + ntask[b];
+        tstart[b + 1] = tstart[b] + (c + tc - 1) / tc;
     }
     const int64_t total = tstart[kMaxBins];
     for (;;) {
@@ -297,14 +339,20 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs A, int stage_elems) {
         t = __shfl(t, 0);
         if ((int64_t)t >= total) break;
         int b = 0;
+        int64_t tb = 0;
 #pragma unroll
         for (int k = 1; k < kMaxBins; ++k)
-            if ((int64_t)t >= tstart[k]) b = k;
+            if ((int64_t)t >= tstart[k]) {
+                b = k;
+                tb = tstart[k];
+            }
         const BinDesc& bd = A.bins[b];
-        const int64_t local = ((int64_t)t - tstart[b]) * bd.task_cells;
+        const int64_t local = ((int64_t)t - tb) * bd.task_cells;
         const int64_t cnt = (int64_t)A.counts[b];
         const int n = (int)(cnt - local < bd.task_cells ? cnt - local : bd.task_cells);
-        batch_dispatch<PREC>(A, bd, (int64_t)A.offs[b] + local, n, lane, gtile, stage, soffs);
+        const int64_t first = (int64_t)A.offs[b] + local;
+        if (bd.variant == 0) batch_dispatch_v<PREC, 0>(A, bd, first, n, lane, gtile, stage, soffs);
+        else batch_dispatch_v<PREC, 1>(A, bd, first, n, lane, gtile, stage, soffs);
     }
 }
 
@@ -317,7 +365,7 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 
 int64_t batch_workspace_bytes(int nseg, int64_t nentries) {
     (void)nseg;
-    return (int64_t)(4 * dev::kMaxBins) * 8 + 256 + nentries * 4;
+    return (int64_t)(4 * dev::kMaxBins) * 8 + 256 + nentries * 12;
 }
 
 static int batch_type(int form, int cell, int degree) {
@@ -348,9 +396,10 @@ coffee_status assemble_batch(int precision, const coffee_segment* segs, int nseg
         const int type = batch_type(s.form, s.cell, s.degree);
         if (type < 0) return COFFEE_E_UNSUPPORTED;
         if (!s.coords || !s.cell_to_vertex || s.nvert < 0 || s.ncells_mesh < 0) return COFFEE_E_INVALID_ARG;
+        if (s.ncells_mesh > INT32_MAX) return COFFEE_E_UNSUPPORTED;
         if (!s.coeff || !s.coeff->values || s.coeff->degree != 1 || s.coeff->ncomp != 1) return COFFEE_E_UNSUPPORTED;
         if (s.variant < 0 || s.variant > 1) return COFFEE_E_INVALID_ARG;
-        if (s.task_cells != 0 && s.task_cells != 64 && s.task_cells != 128 && s.task_cells != 256)
+        if (s.task_cells != 0 && (s.task_cells % 64 != 0 || s.task_cells < 64 || s.task_cells > 1024))
             return COFFEE_E_INVALID_ARG;
         const int q = s.quad_degree >= 0 ? s.quad_degree : 2 * s.degree;
         if (q > 10) return COFFEE_E_INVALID_ARG;
@@ -364,7 +413,7 @@ coffee_status assemble_batch(int precision, const coffee_segment* segs, int nseg
         d.rfrag = rf;
         d.type = type;
         d.variant = s.variant;
-        d.task_cells = s.task_cells ? s.task_cells : 64;
+        d.task_cells = s.task_cells ? s.task_cells : 256;
         int tv = 0, tt = 0;
         if (s.task_cells == 0 && tuned_batch(s.form, s.cell, s.degree, precision, &tv, &tt)) {
             d.variant = tv;
@@ -383,7 +432,8 @@ coffee_status assemble_batch(int precision, const coffee_segment* segs, int nseg
     a.offs = ws + dev::kMaxBins;
     a.cursor = ws + 2 * dev::kMaxBins;
     a.queue = ws + 3 * dev::kMaxBins;
-    a.list = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) + 4 * dev::kMaxBins * 8 + 256);
+    a.boff = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(workspace) + 4 * dev::kMaxBins * 8 + 256);
+    a.bcell = reinterpret_cast<int32_t*>(a.boff + nentries);
     hipStream_t s = (hipStream_t)hip_stream;
     const int ncu = num_cu(devid);
     hipLaunchKernelGGL(dev::k_fill_u64, dim3(1), dim3(64), 0, s, ws, (unsigned long long)0, (int64_t)(4 * dev::kMaxBins));

@@ -19,12 +19,6 @@ namespace dev {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 constexpr int nuniq(int d, int p) { return nsc(d, p) * (nsc(d, p) + 1) / 2; }
 constexpr int ntiles_sym(int d, int p) { return (nuniq(d, p) + 15) / 16; }
 
@@ -72,6 +66,29 @@ struct ScalarWave {
     typename C::frag_t rreg[C::RREG ? C::NT : 1][C::RREG ? C::KS : 1];
 };
 
+// Accumulate n-tiles t0 .. t0 + NTC - 1 of the 16-cell tile whose G rows are
+// in W.gtile.
+template <int FORM, int D, int P, int FD, int PREC, int NTC>
+__device__ inline void scalar_contract(const ScalarWave<FORM, D, P, FD, PREC>& W, int t0,
+                                       typename PrecT<PREC>::acc (&acc)[NTC]) {
+    using C = ScalarCfg<FORM, D, P, FD, PREC>;
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[t] = typename C::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < C::KS; ++s) {
+        const typename C::frag_t a = load_afrag<PREC>(W.gtile, C::ROW, W.lane, s);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) {
+            if (t0 + t < C::NT) {
+                typename C::frag_t bf;
+                if constexpr (C::RREG) bf = W.rreg[t0 + t < C::NT ? t0 + t : 0][s];
+                else bf = W.rf[((t0 + t) * C::KS + s) * 64 + W.lane];
+                acc[t] = mfma<PREC>(a, bf, acc[t]);
+            }
+        }
+    }
+}
+
 // Contract and store one 16-cell tile. FULL: all 16 cells exist, so the code
 // is straight-line with compile-time store counts (the compiler can then track
 // outstanding memory operations exactly instead of draining the store queue
@@ -90,21 +107,7 @@ __device__ inline void scalar_tile(const LinArgs& A, ScalarWave<FORM, D, P, FD, 
 #pragma unroll
     for (int t0 = 0; t0 < NT; t0 += NTC) {
         acc_t acc[NTC];
-#pragma unroll
-        for (int t = 0; t < NTC; ++t) acc[t] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const frag_t a = load_afrag<PREC>(W.gtile, ROW, lane, s);
-#pragma unroll
-            for (int t = 0; t < NTC; ++t) {
-                if (t0 + t < NT) {
-                    frag_t bf;
-                    if constexpr (C::RREG) bf = W.rreg[t0 + t < NT ? t0 + t : 0][s];
-                    else bf = W.rf[((t0 + t) * KS + s) * 64 + lane];
-                    acc[t] = mfma<PREC>(a, bf, acc[t]);
-                }
-            }
-        }
+        scalar_contract<FORM, D, P, FD, PREC, NTC>(W, t0, acc);
         if constexpr (C::STAGE) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {

@@ -454,8 +454,20 @@ static coffee_status svk_table(int dev, int dim, int p, int q, const double** ou
     Tables t;
     if (!t.init(dim, p, q)) return COFFEE_E_INVALID_ARG;
     std::vector<double> h;
-    for (int k = 0; k < t.nq; ++k) h.push_back((double)t.W[k]);
-    for (size_t i = 0; i < t.dphi.size(); ++i) h.push_back((double)t.dphi[i]);
+    if (p == 1) {
+        // P1 on an affine cell: the displacement gradient, hence the whole
+        // integrand, is the same at every point, so the point loop is
+        // invariant (section 3.2's loop-invariant code motion applied to the
+        // whole loop): one point carrying the summed weight.
+        long double w = 0.0L;
+        for (int k = 0; k < t.nq; ++k) w += t.W[k];
+        h.push_back((double)w);
+        for (int al = 0; al < dim; ++al)
+            for (int a = 0; a < t.n; ++a) h.push_back((double)t.dphi[((size_t)al * t.nq + 0) * t.n + a]);
+    } else {
+        for (int k = 0; k < t.nq; ++k) h.push_back((double)t.W[k]);
+        for (size_t i = 0; i < t.dphi.size(); ++i) h.push_back((double)t.dphi[i]);
+    }
     void* d = nullptr;
     if (hipMalloc(&d, h.size() * sizeof(double)) != hipSuccess) return COFFEE_E_NOMEM;
     if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
@@ -478,7 +490,8 @@ void free_svk_tables() {
 
 namespace {
 
-// compiled set: triangles and tetrahedra, P1 (q = 2) and P2 (q = 4)
+// compiled set: triangles and tetrahedra, P1 (q = 2, evaluated at one point
+// with the summed weight) and P2 (q = 4)
 template <int D, int P, int NQ>
 hipError_t launch_svk(int form, int precision, const dev::SvkArgs& a, hipStream_t s, int ncu, bool reverse) {
     const int64_t blocks = (a.ncells + 255) / 256;
@@ -509,9 +522,9 @@ hipError_t launch_svk(int form, int precision, const dev::SvkArgs& a, hipStream_
 hipError_t dispatch_svk(int form, int dim, int p, int q, int precision, const dev::SvkArgs& a, hipStream_t s,
                         int ncu, bool reverse, bool* found) {
     *found = true;
-    if (dim == 2 && p == 1 && q == 2) return launch_svk<2, 1, 4>(form, precision, a, s, ncu, reverse);
+    if (dim == 2 && p == 1 && q == 2) return launch_svk<2, 1, 1>(form, precision, a, s, ncu, reverse);
     if (dim == 2 && p == 2 && q == 4) return launch_svk<2, 2, 9>(form, precision, a, s, ncu, reverse);
-    if (dim == 3 && p == 1 && q == 2) return launch_svk<3, 1, 8>(form, precision, a, s, ncu, reverse);
+    if (dim == 3 && p == 1 && q == 2) return launch_svk<3, 1, 1>(form, precision, a, s, ncu, reverse);
     if (dim == 3 && p == 2 && q == 4) return launch_svk<3, 2, 27>(form, precision, a, s, ncu, reverse);
     *found = false;
     return hipSuccess;

@@ -53,7 +53,7 @@ static coffee_status parse(const char* path) {
             int form, cell, deg, prec, var, tc;
             double ns;
             if (std::sscanf(line, "%*s %d %d %d %d %d %d %lf", &form, &cell, &deg, &prec, &var, &tc, &ns) != 7 ||
-                var < 0 || var > 1 || (tc != 64 && tc != 128 && tc != 256)) {
+                var < 0 || var > 1 || tc < 64 || tc > 1024 || tc % 64 != 0) {
                 st = COFFEE_E_INVALID_ARG;
                 break;
             }

@@ -77,7 +77,7 @@ def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4
     return entries
 
 
-def tune_batch(mb, precision: str = "fp32", variants=(0, 1), task_cells=(64, 128, 256), log=print):
+def tune_batch(mb, precision: str = "fp32", variants=(0, 1), task_cells=(128, 256, 512, 1024), log=print):
     """Best (variant, task_cells) per bin of a mixed batch, timed one bin at a time."""
     import torch
     from . import coffee

@@ -57,7 +57,7 @@ def per_bin_reference(cf, mb, segs, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("variant,task_cells", [(0, 64), (1, 64), (0, 256), (1, 128)])
+@pytest.mark.parametrize("variant,task_cells", [(0, 64), (1, 64), (0, 256), (1, 128), (0, 1024), (1, 512)])
 def test_batch_equals_per_bin_launches(cf, precision, variant, task_cells):
     import torch
     mb = I.mixed_batch(n_tri=24, n_tet=6, tri_counts=(400, 300, 200, 100), tet_counts=(500, 300, 200), seed=7)
