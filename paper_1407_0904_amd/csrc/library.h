@@ -16,7 +16,7 @@ coffee_status assemble_svk(int form, int cell, int degree, int q, int precision,
                            int64_t nvert, const int32_t* c2v, int64_t ncells, const coffee_field* coeffs,
                            const double* constants, int nconst, void* out, void* hip_stream);
 
-int grid_for(int dev, const void* kernel, int64_t nchunks, int default_mult);
+int grid_for(int dev, const void* kernel, int threads, int lds_bytes, int64_t nchunks, int default_mult);
 
 coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, const double* coords, int64_t nvert,
                              const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, int ncoeff,
@@ -30,6 +30,6 @@ int tuned_grid_mult(int form, int cell, int degree, int fd, int prec);
 bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* task_cells);
 void free_svk_tables();
 int num_cu(int dev);
-int blocks_per_cu(int dev, const void* kernel);
+int blocks_per_cu(int dev, const void* kernel, int threads, int lds_bytes);
 
 }  // namespace coffee

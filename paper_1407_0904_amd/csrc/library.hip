@@ -81,16 +81,21 @@ static float bf16_float_host(uint16_t h) {
 
 // Pack reference tensors in MFMA B-fragment order: fragment (t, s) for lane l
 // holds rows k of the K dimension and output column 16 t + l % 16. Columns are
-// the entries ab = a n + b, or for symmetric forms the entries a <= b of the
-// upper triangle in row-major order.
-static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym) {
+// the entries a <= b of the upper triangle in row-major order (symmetric
+// engine), or the entries ab = a n + b in row groups of `rows_per_group` rows,
+// each group starting on a fresh 16-column tile (vector engine).
+static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym, int rows_per_group) {
     const int NS = R.NS, NN = R.NS * R.NS, KR = R.KR;
-    std::vector<int> colmap;
+    std::vector<int> colmap;  // packed column -> entry, -1 for padding
     if (sym) {
         for (int a = 0; a < NS; ++a)
             for (int b = a; b < NS; ++b) colmap.push_back(a * NS + b);
     } else {
-        for (int ab = 0; ab < NN; ++ab) colmap.push_back(ab);
+        for (int a0 = 0; a0 < NS; a0 += rows_per_group) {
+            const int a1 = std::min(NS, a0 + rows_per_group);
+            const int ne = (a1 - a0) * NS, nt = (ne + 15) / 16;
+            for (int c = 0; c < 16 * nt; ++c) colmap.push_back(c < ne ? a0 * NS + c : -1);
+        }
     }
     const int NC = (int)colmap.size();
     const int NT = (NC + 15) / 16;
@@ -103,7 +108,7 @@ static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym) 
             for (int s = 0; s < KS; ++s)
                 for (int l = 0; l < 64; ++l) {
                     const int k = 4 * s + l / 16, c = 16 * t + l % 16;
-                    const long double v = (k < KR && c < NC) ? R.R[(size_t)k * NN + colmap[c]] : 0.0L;
+                    const long double v = (k < KR && c < NC && colmap[c] >= 0) ? R.R[(size_t)k * NN + colmap[c]] : 0.0L;
                     const size_t idx = ((size_t)(t * KS + s) * 64 + l);
                     if (prec == COFFEE_FP64) {
                         double d = (double)v;
@@ -122,7 +127,7 @@ static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym) 
                     for (int jj = 0; jj < 8; ++jj) {
                         const int kp = 32 * s + 8 * (l / 16) + jj, c = 16 * t + l % 16;
                         uint16_t h = 0;
-                        if (kp < KE && c < NC) {
+                        if (kp < KE && c < NC && colmap[c] >= 0) {
                             const int k = kp % KR, part = kp / KR;  // 0: R_hi, 1: R_lo, 2: R_hi
                             const float x = (float)R.R[(size_t)k * NN + colmap[c]];
                             const uint16_t hi = bf16_bits_host(x);
@@ -147,7 +152,8 @@ static coffee_status get_rtable(int dev, int form, int dim, int p, int q, int fd
     }
     RefTensor R;
     if (!build_reference(form, dim, p, q, fd, R)) return COFFEE_E_INVALID_ARG;
-    std::vector<char> buf = pack_fragments(R, prec, uses_scalar_engine(form));
+    const int rpg = dev::vec_rows_per_group(R.NS, dev::vec_group_tiles(prec));
+    std::vector<char> buf = pack_fragments(R, prec, uses_scalar_engine(form), rpg);
     DevTable t;
     t.bytes = buf.size();
     if (hipMalloc(&t.ptr, t.bytes) != hipSuccess) return COFFEE_E_NOMEM;
@@ -164,13 +170,14 @@ coffee_status get_rtable_public(int dev, int form, int dim, int p, int q, int fd
     return get_rtable(dev, form, dim, p, q, fd, prec, out);
 }
 
-int blocks_per_cu(int dev, const void* kernel) {
+int blocks_per_cu(int dev, const void* kernel, int threads, int lds_bytes) {
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceCtx& c = device_ctx(dev);
     auto it = c.occupancy.find(kernel);
     if (it != c.occupancy.end()) return it->second;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds_bytes) != hipSuccess || nb <= 0)
+        nb = 1;
     c.occupancy[kernel] = nb;
     return nb;
 }
@@ -182,15 +189,14 @@ int num_cu(int dev) {
 
 // Launch shape override used by the autotuner: grid = cu * blocks_per_cu * mult
 // rounded to a multiple of 8 (XCD count); mult <= 0 selects the engine's
-// default: the pipelined symmetric engine is persistent (a few resident waves of
-// workgroups), the block engine takes one workgroup per 256-cell chunk.
+// default (1: both engines are persistent, one resident set of workgroups).
 static int t_grid_mult = 0;
 
 int batch_grid_mult() { return t_grid_mult; }
 
-int grid_for(int dev, const void* kernel, int64_t nchunks, int default_mult) {
+int grid_for(int dev, const void* kernel, int threads, int lds_bytes, int64_t nchunks, int default_mult) {
     const int cus = num_cu(dev);
-    const int nb = blocks_per_cu(dev, kernel);
+    const int nb = blocks_per_cu(dev, kernel, threads, lds_bytes);
     int64_t g = (int64_t)cus * nb * (t_grid_mult > 0 ? t_grid_mult : default_mult);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     if (g > nchunks) g = nchunks;
@@ -314,9 +320,9 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     }
     a.rfrag = rf;
     a.out = out;
-    a.nchunks = (ncells + 255) / 256;
+    a.nchunks = (ncells + e->cells_per_chunk - 1) / e->cells_per_chunk;
     const int tuned = tuned_grid_mult(form, cell, degree, fd, precision);
-    const int grid = grid_for(dev, e->kernel, a.nchunks, tuned > 0 ? tuned : (uses_scalar_engine(form) ? 1 : 64));
+    const int grid = grid_for(dev, e->kernel, e->threads, e->lds_bytes, a.nchunks, tuned > 0 ? tuned : 1);
     if (e->launch(a, (hipStream_t)hip_stream, grid) != hipSuccess) return COFFEE_E_HIP;
     return COFFEE_OK;
 }

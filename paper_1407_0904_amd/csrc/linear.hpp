@@ -1,4 +1,5 @@
-// Device engine for linear forms (mass, Helmholtz, elasticity, Burgers Jacobian).
+// Shared device pieces of the assembly engines (mass, Helmholtz, elasticity,
+// Burgers Jacobian).
 //
 // Per cell (paper, section 2, Fig. 1): the Jacobian, its determinant and
 // inverse from the vertex coordinates; coefficient dofs; then the element
@@ -10,12 +11,11 @@
 //     FP64   v_mfma_f64_16x16x4f64
 //     FP32   v_mfma_f32_16x16x4f32
 //     BF16X3 v_mfma_f32_16x16x32_bf16 on [G_hi | G_hi | G_lo] x [R_hi ; R_lo ; R_hi]
-//
-// Work layout: a workgroup of 4 waves takes 256 consecutive cells per step
-// (64 per wave, one cell per lane for the geometry), writes G rows to LDS,
-// then each wave contracts its 64 cells as 4 MFMA row tiles. The reference
-// tensors are pre-packed on the host in MFMA B-fragment order so that each
-// fragment load is one coalesced 512-byte (or 1 KiB) read.
+// The reference tensors are pre-packed on the host in MFMA B-fragment order
+// so that each fragment load is one coalesced 512-byte (or 1 KiB) read.
+// This file holds the gathers, the FP64 geometry, the G builders and their
+// transposes (used by the adjoint), and the MFMA helpers; the engines are
+// scalar.hpp (symmetric single-block forms) and vector.hpp (vector forms).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -460,182 +460,12 @@ __device__ inline typename PrecT<PREC>::frag load_afrag(const typename PrecT<PRE
     }
 }
 
-// ---------------------------------------------------------------- block engine
-
 // Orders the LDS accesses of one wave around a point where its lanes exchange
 // data through LDS.
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int FORM, int D, int P, int FD, int PREC>
-struct BlockCfg {
-    using g_t = typename PrecT<PREC>::gtype;
-    using frag_t = typename PrecT<PREC>::frag;
-    using acc_t = typename PrecT<PREC>::acc;
-    using out_t = typename PrecT<PREC>::otype;
-    static constexpr int NS = nsc(D, P);
-    static constexpr int NN = NS * NS;
-    static constexpr int NC = ncomp_space(FORM, D);
-    static constexpr int N = NC * NS;
-    static constexpr int KR = kref(FORM, D, FD);
-    static constexpr int KS = ksteps(FORM, D, FD, PREC);
-    static constexpr int NT = ntiles(D, P);
-    static constexpr int ROW = GLayout<FORM, D, FD, PREC>::ROW;
-    static constexpr int NFRAG = NT * KS * 64;
-    // Reference fragments live in registers when they are few, else in LDS
-    // (read once per workgroup, shared by its four waves), else in L2.
-    static constexpr bool RREG = NT * KS * (int)(sizeof(frag_t) / 4) <= 64;
-    static constexpr bool RLDS = !RREG && NFRAG * (int)sizeof(frag_t) <= 64 * 1024;
-    // The elasticity form is symmetric: blocks c1 <= c2 are contracted and
-    // block (c2, c1) is written as their transpose.
-    static constexpr bool SYM = FORM == F_ELAST;
-    static constexpr int NTC = NT < 8 ? NT : 8;  // n-tiles held in accumulators at once
-};
-
-// First k-step that can hold a nonzero G entry of block (c1, c2): the
-// off-diagonal blocks of the Burgers Jacobian carry only the E(r, a) terms,
-// which come last in the tensor order, so their leading steps are skipped
-// (structurally zero blocks of the reference products are never contracted).
-template <int FORM, int D, int FD, int PREC, int C1, int C2>
-constexpr int kstep_begin() {
-    if constexpr (FORM == F_BURG && C1 != C2 && PREC != PREC_BF16X3)
-        return (1 + npair(D) + nfield(D, FD) * D) / kstep(PREC);
-    else
-        return 0;
-}
-
-// Contract the 16-cell tile at tile_base for block (c1, c2) against every
-// n-tile of R and store it (and its transpose for a symmetric form).
-template <int FORM, int D, int P, int FD, int PREC, int C1, int C2>
-__device__ inline void block_tile(const LinArgs& A, const typename PrecT<PREC>::gtype* gtile,
-                                  const typename PrecT<PREC>::frag* rsrc,
-                                  const typename PrecT<PREC>::frag (&rreg)[BlockCfg<FORM, D, P, FD, PREC>::RREG
-                                                                             ? BlockCfg<FORM, D, P, FD, PREC>::NT : 1]
-                                                                            [BlockCfg<FORM, D, P, FD, PREC>::RREG
-                                                                             ? BlockCfg<FORM, D, P, FD, PREC>::KS : 1],
-                                  int64_t tile_base, int lane) {
-    using C = BlockCfg<FORM, D, P, FD, PREC>;
-    using frag_t = typename C::frag_t;
-    using acc_t = typename C::acc_t;
-    using out_t = typename C::out_t;
-    constexpr int NS = C::NS, NN = C::NN, N = C::N, KS = C::KS, NT = C::NT, NTC = C::NTC, ROW = C::ROW;
-    constexpr int KB = kstep_begin<FORM, D, FD, PREC, C1, C2>();
-    out_t* out = reinterpret_cast<out_t*>(A.out);
-    const int col = lane & 15;
-#pragma unroll 1
-    for (int t0 = 0; t0 < NT; t0 += NTC) {
-        acc_t acc[NTC];
-#pragma unroll
-        for (int t = 0; t < NTC; ++t) acc[t] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int s = KB; s < KS; ++s) {
-            const frag_t a = load_afrag<PREC>(gtile, ROW, lane, s);
-#pragma unroll
-            for (int t = 0; t < NTC; ++t) {
-                if (t0 + t < NT) {
-                    frag_t b;
-                    if constexpr (C::RREG) b = rreg[t0 + t < NT ? t0 + t : 0][s];
-                    else b = rsrc[((t0 + t) * KS + s) * 64 + lane];
-                    acc[t] = mfma<PREC>(a, b, acc[t]);
-                }
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < NTC; ++t) {
-            const int ab = (t0 + t) * 16 + col;
-            if (t0 + t >= NT || ab >= NN) continue;
-            const int a = ab / NS, b = ab - (ab / NS) * NS;
-            const int64_t o1 = (int64_t)(C1 * NS + a) * N + C2 * NS + b;
-            const int64_t o2 = (int64_t)(C2 * NS + b) * N + C1 * NS + a;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t cell = tile_base + acc_row<PREC>(lane, v);
-                if (cell < A.ncells) {
-                    out_t* base = out + cell * (int64_t)N * N;
-                    const out_t x = (out_t)acc[t][v];
-                    base[o1] = x;
-                    if constexpr (C::SYM && C1 != C2) base[o2] = x;
-                }
-            }
-        }
-    }
-}
-
-template <int FORM, int D, int P, int FD, int PREC, int B>
-__device__ inline void block_step(const LinArgs& A, const CellData<FORM, D, FD>& cd, bool valid,
-                                  typename PrecT<PREC>::gtype* gtile, const typename PrecT<PREC>::frag* rsrc,
-                                  const typename PrecT<PREC>::frag (&rreg)[BlockCfg<FORM, D, P, FD, PREC>::RREG
-                                                                             ? BlockCfg<FORM, D, P, FD, PREC>::NT : 1]
-                                                                            [BlockCfg<FORM, D, P, FD, PREC>::RREG
-                                                                             ? BlockCfg<FORM, D, P, FD, PREC>::KS : 1],
-                                  int64_t wave_base, int lane) {
-    using C = BlockCfg<FORM, D, P, FD, PREC>;
-    constexpr int C1 = B / C::NC, C2 = B % C::NC;
-    if constexpr (!(C::SYM && C1 > C2)) {
-        double G[C::KR];
-        if (valid) build_G<FORM, D, FD, C1, C2>(cd, A, G);
-        else {
-#pragma unroll
-            for (int k = 0; k < C::KR; ++k) G[k] = 0.0;
-        }
-        const int col = lane & 15;
-#pragma unroll 1
-        for (int j = 0; j < 4; ++j) {
-            const int64_t tile_base = wave_base + 16 * j;
-            if (tile_base >= A.ncells) break;  // wave-uniform
-            if ((lane >> 4) == j) put_G_row<FORM, D, FD, PREC>(gtile + col * C::ROW, G);
-            wave_sync();
-            block_tile<FORM, D, P, FD, PREC, C1, C2>(A, gtile, rsrc, rreg, tile_base, lane);
-            wave_sync();
-        }
-    }
-    if constexpr (B + 1 < C::NC * C::NC)
-        block_step<FORM, D, P, FD, PREC, B + 1>(A, cd, valid, gtile, rsrc, rreg, wave_base, lane);
-}
-
-// Vector forms: a wave takes 64 cells per step (one lane per cell for the
-// gathers, the FP64 geometry and the G row of each block), then contracts
-// them as four 16-cell MFMA tiles per block; waves share only the reference
-// fragments, so the persistent loop needs no workgroup barrier.
-template <int FORM, int D, int P, int FD, int PREC>
-__global__ __launch_bounds__(256) void k_linear(LinArgs A) {
-    using C = BlockCfg<FORM, D, P, FD, PREC>;
-    using g_t = typename C::g_t;
-    using frag_t = typename C::frag_t;
-    __shared__ __attribute__((aligned(16))) g_t sG[4][16 * C::ROW];
-    __shared__ __attribute__((aligned(16))) frag_t sR[C::RLDS ? C::NFRAG : 1];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const frag_t* rg = reinterpret_cast<const frag_t*>(A.rfrag);
-    const frag_t* rsrc = rg;
-    if constexpr (C::RLDS) {
-        for (int i = threadIdx.x; i < C::NFRAG; i += 256) sR[i] = rg[i];
-        __syncthreads();
-        rsrc = sR;
-    }
-    frag_t rreg[C::RREG ? C::NT : 1][C::RREG ? C::KS : 1];
-    if constexpr (C::RREG) {
-#pragma unroll
-        for (int t = 0; t < C::NT; ++t)
-#pragma unroll
-            for (int s = 0; s < C::KS; ++s) rreg[t][s] = rg[(t * C::KS + s) * 64 + lane];
-    }
-    // XCD-aware order: consecutive logical workgroups of one XCD (round-robin
-    // dispatch, 8 XCDs) take consecutive chunks of cells.
-    const int64_t G = gridDim.x;
-    const int64_t b = blockIdx.x;
-    const int64_t logical = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
-    for (int64_t chunk = logical; chunk < A.nchunks; chunk += G) {
-        const int64_t wave_base = chunk * 256 + wave * 64;
-        if (wave_base >= A.ncells) break;  // wave-uniform; no barrier follows
-        const int64_t cell = wave_base + lane;
-        const bool valid = cell < A.ncells;
-        CellData<FORM, D, FD> cd;
-        if (valid) load_cell<FORM, D, FD>(A, cell, cd);
-        block_step<FORM, D, P, FD, PREC, 0>(A, cd, valid, sG[wave], rsrc, rreg, wave_base, lane);
-    }
 }
 
 }  // namespace dev

@@ -7,6 +7,7 @@
 
 #include "linear.hpp"
 #include "scalar.hpp"
+#include "vector.hpp"
 
 namespace coffee {
 
@@ -16,10 +17,13 @@ struct LinEntry {
     int form, dim, p, fd, prec;
     LinLaunch launch;
     const void* kernel;
+    int threads;          // workgroup size
+    int lds_bytes;        // dynamic LDS per workgroup
+    int cells_per_chunk;  // LinArgs::nchunks = ceil(ncells / cells_per_chunk)
 };
 
 // Mass and Helmholtz are symmetric single-block forms and use the symmetric
-// engine (scalar.hpp); the vector forms use the block engine (linear.hpp).
+// engine (scalar.hpp); the vector forms use the panel engine (vector.hpp).
 constexpr bool uses_scalar_engine(int form) { return form == dev::F_MASS || form == dev::F_HELM; }
 
 template <int FORM, int D, int P, int FD, int PREC>
@@ -27,21 +31,37 @@ const void* kernel_of() {
     if constexpr (uses_scalar_engine(FORM))
         return reinterpret_cast<const void*>(&dev::k_scalar<FORM, D, P, FD, PREC>);
     else
-        return reinterpret_cast<const void*>(&dev::k_linear<FORM, D, P, FD, PREC>);
+        return reinterpret_cast<const void*>(&dev::k_vector<FORM, D, P, FD, PREC>);
 }
 
+// The vector engine takes its LDS dynamically (it can exceed the 64 KiB of
+// static allocations); the attribute is set once per kernel.
 template <int FORM, int D, int P, int FD, int PREC>
 hipError_t launch_linear(const dev::LinArgs& a, hipStream_t s, int grid) {
-    if constexpr (uses_scalar_engine(FORM))
+    if constexpr (uses_scalar_engine(FORM)) {
         hipLaunchKernelGGL((dev::k_scalar<FORM, D, P, FD, PREC>), dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((dev::k_linear<FORM, D, P, FD, PREC>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        using C = dev::VecCfg<FORM, D, P, FD, PREC>;
+        static const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&dev::k_vector<FORM, D, P, FD, PREC>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+        if (attr != hipSuccess) return attr;
+        hipLaunchKernelGGL((dev::k_vector<FORM, D, P, FD, PREC>), dim3(grid), dim3(C::WAVES * 64), C::LDS_BYTES, s,
+                           a);
+    }
     return hipGetLastError();
 }
 
 template <int FORM, int D, int P, int FD, int PREC>
 LinEntry lin_entry() {
-    return LinEntry{FORM, D, P, FD, PREC, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>()};
+    if constexpr (uses_scalar_engine(FORM)) {
+        return LinEntry{FORM, D, P, FD, PREC, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>(),
+                        256, 0, 256};
+    } else {
+        using C = dev::VecCfg<FORM, D, P, FD, PREC>;
+        return LinEntry{FORM, D, P, FD, PREC, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>(),
+                        C::WAVES * 64, C::LDS_BYTES, C::WAVES * 16};
+    }
 }
 
 // one instance for each precision

@@ -99,6 +99,67 @@ def test_burgers(cf, oracle, d, p, prec):
     assert err < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("form,p", [("elasticity", 2), ("burgers", 2), ("burgers", 1)])
+def test_vector_ragged_counts(cf, oracle, form, p, prec):
+    """Cell counts around the 16-cell tile and the 128-cell chunk of the
+    vector engine (one cell, a partial first tile, full tiles plus a partial
+    one, several chunks plus a tail), on tetrahedra with P1 Lame fields or a
+    vector Burgers state of the trial degree."""
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    rng = np.random.default_rng(90 + p)
+    mesh = I.make_mesh(3, 6, 0.1, rng)  # 1296 cells
+    if form == "elasticity":
+        mu = rng.uniform(1, 10, size=(mesh.nvert, 1))
+        lm = rng.uniform(1, 10, size=(mesh.nvert, 1))
+        cst = []
+    else:
+        w = rng.uniform(-1, 1, size=(mesh.nvert if p == 1 else I.p2_dofmap(mesh.cells, mesh.n, 3)[1], 3))
+        cst = [0.7, 1.3]
+    for n in (1, 15, 17, 48, 133, 1291):
+        sub = I.Mesh(3, mesh.n, mesh.coords, mesh.cells[:n])
+        if form == "elasticity":
+            flds = [I.Field(mu, sub.cells, 1, 1), I.Field(lm, sub.cells, 1, 1)]
+        elif p == 1:
+            flds = [I.Field(w, sub.cells, 1, 3)]
+        else:
+            flds = [I.Field(w, I.p2_dofmap(mesh.cells, mesh.n, 3)[0][:n], 2, 3)]
+        ref = oracle.assemble(form, sub, p, fields=flds, constants=cst)
+        got = assemble_gpu(form, sub, p, flds, constants=cst, precision=prec).cpu().numpy()
+        err = cell_rel_err(got, ref)
+        print(f"{form} p{p} {n} cells {prec}: {err:.3e}")
+        assert err < TOL[prec]
+
+
+def test_full_size_elasticity_p2_tet_sampled(cf, oracle):
+    """The 663,552-cell elasticity P2 tetrahedron workload (P1 Lame fields) in
+    the benchmark's launch configuration: sampled cells against the oracle in
+    every precision, and rigid translations in the kernel of all cells."""
+    import torch
+    from gpu_util import TOL, cell_rel_err, to_dev
+    w = I.workload("elasticity_p2_tet")
+    coords, c2v, dfs = to_dev(w.mesh, w.fields)
+    rng = np.random.default_rng(12)
+    E = w.mesh.ncells
+    sample = np.unique(np.concatenate([[0, 1, 15, 16, 127, 128, E - 1], rng.integers(0, E, 1500)]))
+    ref = oracle.assemble(w.form, w.mesh, 2, w.quad_degree, fields=w.fields, cells=sample)
+    idx = torch.as_tensor(sample, device=coords.device)
+    for prec in PRECS:
+        out = cf.coffee_assemble(w.form, 3, 2, coords, c2v, coeffs=dfs, quad_degree=w.quad_degree, precision=prec)
+        torch.cuda.synchronize()
+        got = out[idx].cpu().numpy()
+        err = cell_rel_err(got, ref)
+        print(f"elasticity_p2_tet full {prec}: {err:.3e}")
+        assert err < TOL[prec]
+        if prec == "fp64":
+            # a rigid translation along x (component block 0) is in the kernel of every A_e
+            t = torch.zeros(30, dtype=torch.float64, device=coords.device)
+            t[:10] = 1.0
+            r = (out @ t).abs().amax(dim=1) / out.abs().amax(dim=(1, 2))
+            assert float(r.max()) < 1e-12
+        del out
+
+
 def test_edge_cases(cf, oracle):
     """Empty input, a single cell, exactly one chunk, one chunk + 1, cell-major fields."""
     import torch
