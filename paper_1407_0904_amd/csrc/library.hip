@@ -152,7 +152,7 @@ static coffee_status get_rtable(int dev, int form, int dim, int p, int q, int fd
     }
     RefTensor R;
     if (!build_reference(form, dim, p, q, fd, R)) return COFFEE_E_INVALID_ARG;
-    const int rpg = dev::vec_rows_per_group(R.NS, dev::vec_group_tiles(prec));
+    const int rpg = dev::vec_rows_per_group(R.NS, dev::vec_group_tiles(form, prec));
     std::vector<char> buf = pack_fragments(R, prec, uses_scalar_engine(form), rpg);
     DevTable t;
     t.bytes = buf.size();

@@ -8,15 +8,18 @@
 // the MFMA products) and completes it before the next tile, panel by panel:
 // panel c is rows c n .. c n + n - 1 of every cell's tensor, NC n values per
 // row, so a panel is one contiguous range of each cell's tensor. A panel is
-// computed in row groups (rows a0 .. a1 - 1, chosen so that the group's
-// entries a n + b start on a 16-column boundary of R): for each c' the wave
+// computed in row groups (a few rows, so that the accumulators of all NC
+// blocks of the group stay in registers; R is packed group by group): the wave
 // builds G_cc' of its 16 cells in LDS (lane (cell, g) writes the entries of
 // the coefficient dofs r = g, g + 4, ...), contracts it against R's column
-// tiles of the group, and keeps the accumulators of all NC blocks; then the
-// group's rows are transposed through LDS and leave as 16-byte stores that
-// cover whole contiguous ranges of 4 (or 16) cells. Writing every output line
-// completely, once, is what keeps the store traffic at the algorithmic bytes:
-// partial lines written at different times reach HBM more than once.
+// tiles of the group (all NC blocks in one k-loop that loads each R fragment
+// once, when their G rows fit in LDS), then the group's rows are transposed
+// through LDS and leave as 16-byte stores covering whole contiguous ranges of
+// 4 (or 16) cells. Writing every output line completely, once, keeps the
+// store traffic at the algorithmic bytes: partial lines written at different
+// times reach HBM more than once. The whole tile is unrolled, so that the
+// wait for the next tile's prefetched gathers does not wait for this tile's
+// stores (one in-order counter covers loads and stores).
 #pragma once
 #include "linear.hpp"
 
@@ -34,9 +37,11 @@ __host__ __device__ constexpr int vec_rows_per_group(int ns, int tb) {
     return r < 1 ? 1 : (r > ns ? ns : r);
 }
 
-// Column tiles per row group: the FP64 accumulators (two registers per value)
-// get fewer, so that two waves fit on a SIMD.
-__host__ __device__ constexpr int vec_group_tiles(int prec) { return prec == PREC_F64 ? 2 : 4; }
+// Column tiles per row group: the FP64 Burgers kernel, whose lanes also hold
+// three state vectors, gets fewer, so that two waves fit on a SIMD.
+__host__ __device__ constexpr int vec_group_tiles(int form, int prec) {
+    return (prec == PREC_F64 && form == F_BURG) ? 2 : 4;
+}
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
@@ -65,7 +70,7 @@ struct VecCfg {
     static constexpr int ROW = GLayout<FORM, D, FD, PREC>::ROW;
     static constexpr int NF = VLane<FORM, D, FD>::NF;
     static constexpr int RPL = VLane<FORM, D, FD>::RPL;
-    static constexpr int TB = vec_group_tiles(PREC);
+    static constexpr int TB = vec_group_tiles(FORM, PREC);
     static constexpr int RGR = vec_rows_per_group(NS, TB);
     static constexpr int NG = (NS + RGR - 1) / RGR;
     static constexpr int row0(int g) { return g * RGR; }
@@ -80,14 +85,21 @@ struct VecCfg {
     static constexpr int RBYTES = NFRAG * (int)sizeof(frag_t);
     static constexpr bool RREG = NTP * KS * (int)(sizeof(frag_t) / 4) <= 32;
     static constexpr bool RLDS = !RREG && RBYTES <= 64 * 1024;
+    // 8 waves: two per SIMD, which is what the registers allow
     static constexpr int WAVES = 8;
-    // output staging: 16 cells per pass when that takes at most 12 KiB, else 4
+    // output staging: 16 cells per pass when that takes at most 8 KiB, else 4
     static constexpr int SLOT = RGMAX * N;  // values of one cell's row group
-    static constexpr int CPP = 16 * SLOT * (int)sizeof(out_t) <= 12288 ? 16 : 4;
+    static constexpr int CPP = 16 * SLOT * (int)sizeof(out_t) <= 8192 ? 16 : 4;
     static constexpr int STAGE_BYTES = CPP * SLOT * (int)sizeof(out_t);
     static constexpr int GBUF_BYTES = 16 * ROW * (int)sizeof(g_t);
-    static constexpr int WAVE_BYTES = (cmax(STAGE_BYTES, GBUF_BYTES) + 15) / 16 * 16;
     static constexpr int RLDS_BYTES = RLDS ? (RBYTES + 15) / 16 * 16 : 0;
+    // merged blocks: the G rows of all NC blocks of a row group are built
+    // together and contracted in one k-loop that loads each reference
+    // fragment once for the NC blocks (a third of the fragment traffic, and NC
+    // times the MFMAs per wait), when the NC G buffers fit the LDS budget
+    static constexpr bool MERGED =
+        RLDS_BYTES + WAVES * ((cmax(STAGE_BYTES, NC * GBUF_BYTES) + 15) / 16 * 16) <= 160 * 1024;
+    static constexpr int WAVE_BYTES = (cmax(STAGE_BYTES, (MERGED ? NC : 1) * GBUF_BYTES) + 15) / 16 * 16;
     static constexpr int LDS_BYTES = RLDS_BYTES + WAVES * WAVE_BYTES;
     // 16-byte stores need every group's range and the cell stride aligned
     static constexpr int PER16 = 16 / (int)sizeof(out_t);
@@ -132,6 +144,7 @@ template <int FORM, int D, int FD>
 struct VCell {
     using C = VLane<FORM, D, FD>;
     double K[D][D];
+    double M[D][D];  // K K^T
     double ad;
     double f[C::NFLD][C::RPL][C::WC];
 };
@@ -187,6 +200,15 @@ __device__ inline void vcell_from_raw(const VRaw<FORM, D, FD>& rw, VCell<FORM, D
     for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j < D; ++j) cd.K[i][j] = g.K[i][j];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) t += g.K[a][i] * g.K[b][i];
+            cd.M[a][b] = t;
+        }
     cd.ad = g.adet;
     if constexpr (FD > 0) {
 #pragma unroll
@@ -227,56 +249,46 @@ __device__ inline double pick(const double (&x)[D], int c) {
     return v;
 }
 
-// Lane (cell row, group g) writes its share of G_{c1 c2} for its cell (same
+// Lane (cell row, group g) writes its share of G_{C1 C2} for its cell (same
 // entries and order as build_G in linear.hpp). Invalid cells get zero rows.
-template <int FORM, int D, int FD, int PREC>
-__device__ inline void vec_put_G(const LinArgs& A, const VCell<FORM, D, FD>& cd, bool valid, int c1, int c2,
+template <int FORM, int D, int FD, int PREC, int C1, int C2>
+__device__ inline void vec_put_G(const LinArgs& A, const VCell<FORM, D, FD>& cd, bool valid,
                                  typename PrecT<PREC>::gtype* row, int g) {
     using C = VLane<FORM, D, FD>;
     constexpr int KR = kref(FORM, D, FD), NF = C::NF, KS = ksteps(FORM, D, FD, PREC);
     const auto& K = cd.K;
+    const auto& M = cd.M;
     const double ad = valid ? cd.ad : 0.0;
-    double k1[D], k2[D];  // columns c1 and c2 of K
+    constexpr bool diag = C1 == C2;
+    double k1[D];  // column C1 of K
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        k1[a] = pick<D>(K[a], c1);
-        k2[a] = pick<D>(K[a], c2);
-    }
-    double M[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) s += K[a][i] * K[b][i];
-            M[a][b] = s;
-        }
+    for (int a = 0; a < D; ++a) k1[a] = K[a][C1];
     if constexpr (FORM == F_ELAST) {
 #pragma unroll
         for (int j = 0; j < C::RPL; ++j) {
             const int r = g + 4 * j;
             if (r < NF) {
-                const double mu = FD > 0 ? cd.f[0][j][0] : A.c0;
-                const double lm = FD > 0 ? cd.f[1][j][0] : A.c1;
+                const double mu = ad * (FD > 0 ? cd.f[0][j][0] : A.c0);
+                const double lm = ad * (FD > 0 ? cd.f[1][j][0] : A.c1);
 #pragma unroll
                 for (int a = 0; a < D; ++a)
 #pragma unroll
                     for (int b = 0; b < D; ++b) {
-                        const double kk = c1 == c2 ? M[a][b] : 0.0;
+                        const double kk = diag ? M[a][b] : 0.0;
                         put_g<PREC, KR>(row, r * D * D + a * D + b,
-                                        ad * (mu * (kk + k2[a] * k1[b]) + lm * k1[a] * k2[b]));
+                                        mu * (kk + K[a][C2] * k1[b]) + lm * k1[a] * K[b][C2]);
                     }
             }
         }
     } else {  // F_BURG
         if (g == 0) {
-            put_g<PREC, KR>(row, 0, c1 == c2 ? ad * A.c1 : 0.0);
+            put_g<PREC, KR>(row, 0, diag ? ad * A.c1 : 0.0);
             int t = 1;
+            const double sc = ad * A.c0;
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int b = a; b < D; ++b) put_g<PREC, KR>(row, t++, c1 == c2 ? ad * A.c0 * M[a][b] : 0.0);
+                for (int b = a; b < D; ++b) put_g<PREC, KR>(row, t++, diag ? sc * M[a][b] : 0.0);
         }
         constexpr int OC = 1 + npair(D), OE = OC + NF * D;
 #pragma unroll
@@ -284,13 +296,14 @@ __device__ inline void vec_put_G(const LinArgs& A, const VCell<FORM, D, FD>& cd,
             const int r = g + 4 * j;
             if (r < NF) {
                 const double* w = cd.f[0][j];
+                const double wc = ad * cd.f[0][j][C1];
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    double s = 0.0;
+                    double t = 0.0;
 #pragma unroll
-                    for (int i = 0; i < D; ++i) s += w[i] * K[a][i];
-                    put_g<PREC, KR>(row, OC + r * D + a, c1 == c2 ? ad * s : 0.0);
-                    put_g<PREC, KR>(row, OE + r * D + a, ad * pick<D>(cd.f[0][j], c1) * k2[a]);
+                    for (int i = 0; i < D; ++i) t += w[i] * K[a][i];
+                    put_g<PREC, KR>(row, OC + r * D + a, diag ? ad * t : 0.0);
+                    put_g<PREC, KR>(row, OE + r * D + a, wc * K[a][C2]);
                 }
             }
         }
@@ -327,8 +340,8 @@ __device__ constexpr int slot_row(int s, int v) {
 
 // Store the staged rows of the cells of one pass: slot s holds rows a0 .. a1-1
 // of panel c (contiguous in the output) of cell tile_base + row(s).
-template <int FORM, int D, int P, int FD, int PREC, bool FULL, int GI>
-__device__ inline void vec_store_pass(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W, int c, int v,
+template <int FORM, int D, int P, int FD, int PREC, bool FULL, int GI, int c>
+__device__ inline void vec_store_pass(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W, int v,
                                       int64_t tile_base) {
     using C = VecCfg<FORM, D, P, FD, PREC>;
     using out_t = typename C::out_t;
@@ -341,41 +354,126 @@ __device__ inline void vec_store_pass(const LinArgs& A, const VecWave<FORM, D, P
     out_t* tb = reinterpret_cast<out_t*>(A.out) + tile_base * (int64_t)(N * N) + (int64_t)(c * NS + a0) * N;
     int lane = W.lane;
     asm volatile("" : "+v"(lane));
+    // lanes 16 j .. 16 j + 15 take slot 4 sg + j (sg = slot quad), consecutive
+    // 16-byte chunks (or values) of that slot's contiguous range
+    const int sl = lane >> 4, ql = lane & 15;
     auto row_of = [&](int s) -> int { return CPP == 16 ? s : slot_row<PREC>(s, v); };
-    if constexpr (C::VEC16) {
-        constexpr int Q = L / C::PER16;  // 16-byte chunks per slot
-        constexpr int TOT = CPP * Q;
-        const vu32x4* s4 = reinterpret_cast<const vu32x4*>(W.stage);
+    constexpr int CH = C::VEC16 ? L / C::PER16 : L;  // chunks per slot
 #pragma unroll
-        for (int i0 = 0; i0 < TOT; i0 += 64) {
-            const int i = i0 + lane;
-            if (i0 + 64 <= TOT || i < TOT) {
-                const int s = i / Q, q = i - (i / Q) * Q;
-                const int r = row_of(s);
-                const vu32x4 x = s4[s * (C::SLOT / C::PER16) + q];
-                if (FULL || tile_base + r < A.ncells)
+    for (int sg = 0; sg < CPP / 4; ++sg) {
+        const int s = 4 * sg + sl;
+        const int r = row_of(s);
+        const bool ok = FULL || tile_base + r < A.ncells;
+#pragma unroll
+        for (int q0 = 0; q0 < CH; q0 += 16) {
+            const int q = q0 + ql;
+            if ((q0 + 16 <= CH || q < CH) && ok) {
+                if constexpr (C::VEC16) {
+                    const vu32x4 x = reinterpret_cast<const vu32x4*>(W.stage)[s * (C::SLOT / C::PER16) + q];
                     *reinterpret_cast<vu32x4*>(tb + (uint32_t)(r * (N * N) + q * C::PER16)) = x;
-            }
-        }
-    } else {
-        constexpr int TOT = CPP * L;
-#pragma unroll
-        for (int i0 = 0; i0 < TOT; i0 += 64) {
-            const int i = i0 + lane;
-            if (i0 + 64 <= TOT || i < TOT) {
-                const int s = i / L, e = i - (i / L) * L;
-                const int r = row_of(s);
-                const out_t x = W.stage[s * C::SLOT + e];
-                if (FULL || tile_base + r < A.ncells) tb[(uint32_t)(r * (N * N) + e)] = x;
+                } else {
+                    tb[(uint32_t)(r * (N * N) + q)] = W.stage[s * C::SLOT + q];
+                }
             }
         }
     }
 }
 
+// Contract block (c, C2) of row group GI into acc[C2], then the next block.
+template <int FORM, int D, int P, int FD, int PREC, int GI, int c, int C2>
+__device__ inline void vec_blocks(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W,
+                                  const VCell<FORM, D, FD>& cd, bool valid, int lane,
+                                  typename PrecT<PREC>::acc (&acc)[D][VecCfg<FORM, D, P, FD, PREC>::tiles_of(GI)]) {
+    using C = VecCfg<FORM, D, P, FD, PREC>;
+    using acc_t = typename C::acc_t;
+    using frag_t = typename C::frag_t;
+    constexpr int KS = C::KS, ROW = C::ROW;
+    constexpr int t0 = C::tile_off(GI), NTG = C::tiles_of(GI);
+    // keeps the scheduler from building the G rows of later blocks early
+    __builtin_amdgcn_sched_barrier(0);
+    vec_put_G<FORM, D, FD, PREC, c, C2>(A, cd, valid, W.gbuf + (lane & 15) * ROW, W.g);
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < NTG; ++t) acc[C2][t] = acc_t{0, 0, 0, 0};
+    constexpr int kb = vec_kstep_begin<FORM, D, FD, PREC>(c, C2);
+    if constexpr (C::RREG) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (s < kb) continue;
+            const frag_t a = load_afrag<PREC>(W.gbuf, ROW, lane, s);
+#pragma unroll
+            for (int t = 0; t < NTG; ++t) acc[C2][t] = mfma<PREC>(a, W.rreg[t0 + t][s], acc[C2][t]);
+        }
+    } else {
+        // a rolled loop: unrolled, the scheduler hoists every fragment load
+        // of the block and runs out of registers
+#pragma unroll 1
+        for (int s = kb; s < KS; ++s) {
+            const frag_t a = load_afrag<PREC>(W.gbuf, ROW, lane, s);
+            frag_t b[NTG];
+#pragma unroll
+            for (int t = 0; t < NTG; ++t) b[t] = W.rsrc[((t0 + t) * KS + s) * 64 + lane];
+#pragma unroll
+            for (int t = 0; t < NTG; ++t) acc[C2][t] = mfma<PREC>(a, b[t], acc[C2][t]);
+        }
+    }
+    wave_sync();
+    if constexpr (C2 + 1 < D) vec_blocks<FORM, D, P, FD, PREC, GI, c, C2 + 1>(A, W, cd, valid, lane, acc);
+}
+
+// Build the G rows of block (c, C2) into its own buffer, then the next block.
+template <int FORM, int D, int P, int FD, int PREC, int c, int C2>
+__device__ inline void vec_put_G_all(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W,
+                                     const VCell<FORM, D, FD>& cd, bool valid, int lane) {
+    using C = VecCfg<FORM, D, P, FD, PREC>;
+    vec_put_G<FORM, D, FD, PREC, c, C2>(A, cd, valid, W.gbuf + C2 * 16 * C::ROW + (lane & 15) * C::ROW, W.g);
+    if constexpr (C2 + 1 < D) vec_put_G_all<FORM, D, P, FD, PREC, c, C2 + 1>(A, W, cd, valid, lane);
+}
+
+// All NC blocks (c, c2) of row group GI in one k-loop: each step loads the
+// group's reference fragments once and the NC blocks' G fragments.
+template <int FORM, int D, int P, int FD, int PREC, int GI, int c>
+__device__ inline void vec_blocks_merged(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W,
+                                         const VCell<FORM, D, FD>& cd, bool valid, int lane,
+                                         typename PrecT<PREC>::acc (&acc)[D][VecCfg<FORM, D, P, FD, PREC>::tiles_of(GI)]) {
+    using C = VecCfg<FORM, D, P, FD, PREC>;
+    using acc_t = typename C::acc_t;
+    using frag_t = typename C::frag_t;
+    constexpr int KS = C::KS, ROW = C::ROW, NC = C::NC;
+    constexpr int t0 = C::tile_off(GI), NTG = C::tiles_of(GI);
+    __builtin_amdgcn_sched_barrier(0);
+    vec_put_G_all<FORM, D, P, FD, PREC, c, 0>(A, W, cd, valid, lane);
+    wave_sync();
+#pragma unroll
+    for (int c2 = 0; c2 < NC; ++c2)
+#pragma unroll
+        for (int t = 0; t < NTG; ++t) acc[c2][t] = acc_t{0, 0, 0, 0};
+    // unrolled (immediate fragment offsets), one scheduling region per step
+    // so that the loads of one step are not all hoisted to the top
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        frag_t b[NTG];
+#pragma unroll
+        for (int t = 0; t < NTG; ++t) {
+            if constexpr (C::RREG) b[t] = W.rreg[t0 + t][s];
+            else b[t] = W.rsrc[((t0 + t) * KS + s) * 64 + lane];
+        }
+#pragma unroll
+        for (int c2 = 0; c2 < NC; ++c2) {
+            if (s < vec_kstep_begin<FORM, D, FD, PREC>(c, c2)) continue;
+            const frag_t a = load_afrag<PREC>(W.gbuf + c2 * 16 * ROW, ROW, lane, s);
+#pragma unroll
+            for (int t = 0; t < NTG; ++t) acc[c2][t] = mfma<PREC>(a, b[t], acc[c2][t]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_sync();
+}
+
 // Panel c, row group GI of the tile at tile_base.
-template <int FORM, int D, int P, int FD, int PREC, bool FULL, int GI>
+template <int FORM, int D, int P, int FD, int PREC, bool FULL, int GI, int c>
 __device__ inline void vec_group(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W,
-                                 const VCell<FORM, D, FD>& cd, bool valid, int c, int64_t tile_base) {
+                                 const VCell<FORM, D, FD>& cd, bool valid, int64_t tile_base) {
     using C = VecCfg<FORM, D, P, FD, PREC>;
     using acc_t = typename C::acc_t;
     using frag_t = typename C::frag_t;
@@ -387,38 +485,8 @@ __device__ inline void vec_group(const LinArgs& A, const VecWave<FORM, D, P, FD,
     asm volatile("" : "+v"(lane));  // lane-derived offsets: recomputed per group, not hoisted
     const int col = lane & 15;
     acc_t acc[NC][NTG];
-#pragma unroll
-    for (int c2 = 0; c2 < NC; ++c2) {
-        // keeps the scheduler from building the G rows of later blocks early
-        __builtin_amdgcn_sched_barrier(0);
-        vec_put_G<FORM, D, FD, PREC>(A, cd, valid, c, c2, W.gbuf + col * ROW, W.g);
-        wave_sync();
-#pragma unroll
-        for (int t = 0; t < NTG; ++t) acc[c2][t] = acc_t{0, 0, 0, 0};
-        const int kb = vec_kstep_begin<FORM, D, FD, PREC>(c, c2);
-        if constexpr (C::RREG) {
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                if (s < kb) continue;
-                const frag_t a = load_afrag<PREC>(W.gbuf, ROW, lane, s);
-#pragma unroll
-                for (int t = 0; t < NTG; ++t) acc[c2][t] = mfma<PREC>(a, W.rreg[t0 + t][s], acc[c2][t]);
-            }
-        } else {
-            // a rolled loop: unrolled, the scheduler hoists every fragment
-            // load of the block and runs out of registers
-#pragma unroll 1
-            for (int s = kb; s < KS; ++s) {
-                const frag_t a = load_afrag<PREC>(W.gbuf, ROW, lane, s);
-                frag_t b[NTG];
-#pragma unroll
-                for (int t = 0; t < NTG; ++t) b[t] = W.rsrc[((t0 + t) * KS + s) * 64 + lane];
-#pragma unroll
-                for (int t = 0; t < NTG; ++t) acc[c2][t] = mfma<PREC>(a, b[t], acc[c2][t]);
-            }
-        }
-        wave_sync();
-    }
+    if constexpr (C::MERGED) vec_blocks_merged<FORM, D, P, FD, PREC, GI, c>(A, W, cd, valid, lane, acc);
+    else vec_blocks<FORM, D, P, FD, PREC, GI, c, 0>(A, W, cd, valid, lane, acc);
     // transpose through LDS: group entry 16 t + col of block (c, c2) is
     // (a, b) = (a0, 0) + divmod(16 t + col, n), row a, column c2 n + b of the panel
     constexpr int NPASS = C::CPP == 16 ? 1 : 4;
@@ -442,25 +510,30 @@ __device__ inline void vec_group(const LinArgs& A, const VecWave<FORM, D, P, FD,
             }
         }
         wave_sync();
-        vec_store_pass<FORM, D, P, FD, PREC, FULL, GI>(A, W, c, pass, tile_base);
+        vec_store_pass<FORM, D, P, FD, PREC, FULL, GI, c>(A, W, pass, tile_base);
         wave_sync();
     }
 }
 
-template <int FORM, int D, int P, int FD, int PREC, bool FULL, int GI>
-__device__ inline void vec_groups(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W,
-                                  const VCell<FORM, D, FD>& cd, bool valid, int c, int64_t tile_base) {
-    vec_group<FORM, D, P, FD, PREC, FULL, GI>(A, W, cd, valid, c, tile_base);
+// Panels c .. D-1 (row groups GI .. NG-1 of panel c first). Everything is
+// unrolled, so the number of stores between a prefetch load and its use is a
+// compile-time count and the wait for the load need not wait for the stores
+// (loads and stores share one in-order counter).
+template <int FORM, int D, int P, int FD, int PREC, bool FULL, int c, int GI>
+__device__ inline void vec_panels(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W,
+                                  const VCell<FORM, D, FD>& cd, bool valid, int64_t tile_base) {
+    vec_group<FORM, D, P, FD, PREC, FULL, GI, c>(A, W, cd, valid, tile_base);
     if constexpr (GI + 1 < VecCfg<FORM, D, P, FD, PREC>::NG)
-        vec_groups<FORM, D, P, FD, PREC, FULL, GI + 1>(A, W, cd, valid, c, tile_base);
+        vec_panels<FORM, D, P, FD, PREC, FULL, c, GI + 1>(A, W, cd, valid, tile_base);
+    else if constexpr (c + 1 < D)
+        vec_panels<FORM, D, P, FD, PREC, FULL, c + 1, 0>(A, W, cd, valid, tile_base);
 }
 
 template <int FORM, int D, int P, int FD, int PREC, bool FULL>
 __device__ inline void vec_tile(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W,
                                 const VCell<FORM, D, FD>& cd, int64_t tile_base) {
     const bool valid = FULL || tile_base + (W.lane & 15) < A.ncells;
-#pragma unroll 1
-    for (int c = 0; c < D; ++c) vec_groups<FORM, D, P, FD, PREC, FULL, 0>(A, W, cd, valid, c, tile_base);
+    vec_panels<FORM, D, P, FD, PREC, FULL, 0, 0>(A, W, cd, valid, tile_base);
 }
 
 // Persistent kernel: each workgroup takes chunks of WAVES tiles (XCD-aware
@@ -469,10 +542,9 @@ __device__ inline void vec_tile(const LinArgs& A, const VecWave<FORM, D, P, FD, 
 // (indices two tiles ahead, coordinates and coefficient values one ahead).
 // LinArgs::nchunks = ceil(ncells / (16 WAVES)).
 template <int FORM, int D, int P, int FD, int PREC>
-__global__ __launch_bounds__(512) void k_vector(LinArgs A) {
+__global__ __launch_bounds__((VecCfg<FORM, D, P, FD, PREC>::WAVES * 64)) void k_vector(LinArgs A) {
     using C = VecCfg<FORM, D, P, FD, PREC>;
     using frag_t = typename C::frag_t;
-    static_assert(C::WAVES * 64 == 512, "launch bounds");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     VecWave<FORM, D, P, FD, PREC> W;
@@ -485,7 +557,7 @@ __global__ __launch_bounds__(512) void k_vector(LinArgs A) {
     W.rsrc = rg;
     if constexpr (C::RLDS) {
         frag_t* sR = reinterpret_cast<frag_t*>(lds);
-        for (int i = threadIdx.x; i < C::NFRAG; i += 512) sR[i] = rg[i];
+        for (int i = threadIdx.x; i < C::NFRAG; i += C::WAVES * 64) sR[i] = rg[i];
         __syncthreads();
         W.rsrc = sR;
     }
