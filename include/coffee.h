@@ -175,8 +175,8 @@ typedef struct {
  * Entry i of the batch is cell cell_of[i] of segment seg_of[i]; its element
  * tensor is written at out + out_offset[i] (elements, FP64 or FP32 by
  * precision; FP32 and FP64 supported). The entries are binned on the device
- * (histogram, prefix sum, scatter of each entry's cell index and output offset
- * into per-bin ranges of the workspace), then one persistent kernel drains a
+ * (histograms, prefix sums, stable scatter of each entry's cell index and
+ * output offset into per-bin ranges of the workspace), then one persistent kernel drains a
  * queue of bin tasks in segment order (put the costliest bins first). Output
  * regions of different entries must not overlap; cell_of[i] must index a cell
  * of segment seg_of[i]'s mesh. Up to 16 segments. All arrays are device memory;
@@ -189,7 +189,21 @@ coffee_status coffee_assemble_batch(int precision, const coffee_segment* segs, i
                                     const int64_t* cell_of, const int64_t* out_offset, int64_t nentries,
                                     void* out, void* workspace, int64_t workspace_bytes, void* hip_stream);
 
-/* Workspace bytes of coffee_assemble_batch. */
+/* The same mixed batch with the output layout chosen by the library: the
+ * element tensors of segment 0 first, then segment 1, ..., each segment's
+ * tensors contiguous and in increasing entry order, so that every tensor is
+ * written as whole contiguous stores. out_offset (device, [nentries], int64)
+ * is an output: out_offset[i] receives the element offset of entry i's tensor.
+ * out must hold sum_i n_seg_of[i]^2 elements (16-byte aligned); the binning is
+ * deterministic (the layout depends only on seg_of). Workspace, precision,
+ * segments and errors as coffee_assemble_batch; the segments' variant is
+ * ignored (every bin uses contiguous staged stores). */
+coffee_status coffee_assemble_batch_packed(int precision, const coffee_segment* segs, int nseg,
+                                           const int32_t* seg_of, const int64_t* cell_of, int64_t nentries,
+                                           void* out, int64_t* out_offset, void* workspace,
+                                           int64_t workspace_bytes, void* hip_stream);
+
+/* Workspace bytes of coffee_assemble_batch and coffee_assemble_batch_packed. */
 int64_t coffee_batch_workspace_size(int nseg, int64_t nentries);
 
 /* Checks every cell: writes to *first_bad (device int64) the smallest cell

@@ -64,6 +64,8 @@ def _load():
     L.coffee_shutdown.restype = None
     L.coffee_assemble_batch.argtypes = [i32, vp, i32, vp, vp, vp, i64, vp, vp, i64, vp]
     L.coffee_assemble_batch.restype = i32
+    L.coffee_assemble_batch_packed.argtypes = [i32, vp, i32, vp, vp, i64, vp, vp, vp, i64, vp]
+    L.coffee_assemble_batch_packed.restype = i32
     L.coffee_batch_workspace_size.argtypes = [i32, i64]
     L.coffee_batch_workspace_size.restype = i64
     L.coffee_load_tuning.argtypes = [C.c_char_p]
@@ -228,17 +230,7 @@ def coffee_batch_workspace_size(nseg: int, nentries: int) -> int:
     return int(_lib.coffee_batch_workspace_size(int(nseg), int(nentries)))
 
 
-def coffee_assemble_batch(segments, seg_of: torch.Tensor, cell_of: torch.Tensor, out_offset: torch.Tensor,
-                          total_elems: int, precision: str = "fp32", out: torch.Tensor | None = None,
-                          workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Packed element tensors of a mixed batch (coffee_assemble_batch)."""
-    odt = torch.float64 if precision == "fp64" else torch.float32
-    dev = seg_of.device
-    n = seg_of.shape[0]
-    if out is None:
-        out = torch.empty(total_elems, dtype=odt, device=dev)
-    if workspace is None:
-        workspace = torch.empty(coffee_batch_workspace_size(len(segments), n), dtype=torch.uint8, device=dev)
+def _segments(segments):
     segs = (_Segment * len(segments))()
     fields = (_Field * len(segments))()
     for i, sg in enumerate(segments):
@@ -250,12 +242,52 @@ def coffee_assemble_batch(segments, seg_of: torch.Tensor, cell_of: torch.Tensor,
                            _dptr(sg.coords, torch.float64, "coords"), sg.coords.shape[0],
                            _dptr(sg.cell_to_vertex, torch.int32, "cell_to_vertex"), sg.cell_to_vertex.shape[0],
                            C.addressof(fields[i]), int(sg.variant), int(sg.task_cells))
+    return segs, fields  # fields must outlive the call
+
+
+def coffee_assemble_batch(segments, seg_of: torch.Tensor, cell_of: torch.Tensor, out_offset: torch.Tensor,
+                          total_elems: int, precision: str = "fp32", out: torch.Tensor | None = None,
+                          workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Packed element tensors of a mixed batch at the caller's offsets (coffee_assemble_batch)."""
+    odt = torch.float64 if precision == "fp64" else torch.float32
+    dev = seg_of.device
+    n = seg_of.shape[0]
+    if out is None:
+        out = torch.empty(total_elems, dtype=odt, device=dev)
+    if workspace is None:
+        workspace = torch.empty(coffee_batch_workspace_size(len(segments), n), dtype=torch.uint8, device=dev)
+    segs, _keep = _segments(segments)
     st = _lib.coffee_assemble_batch(PRECISIONS[precision], segs, len(segments),
                                     _dptr(seg_of, torch.int32, "seg_of"), _dptr(cell_of, torch.int64, "cell_of"),
                                     _dptr(out_offset, torch.int64, "out_offset"), n, _dptr(out, odt, "out"),
                                     workspace.data_ptr(), workspace.numel(), _stream(stream))
     _check(st, "coffee_assemble_batch")
     return out
+
+
+def coffee_assemble_batch_packed(segments, seg_of: torch.Tensor, cell_of: torch.Tensor, total_elems: int,
+                                 precision: str = "fp32", out: torch.Tensor | None = None,
+                                 out_offset: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                                 stream=None):
+    """Element tensors of a mixed batch in the library's segment-major layout
+    (coffee_assemble_batch_packed); returns (out, out_offset)."""
+    odt = torch.float64 if precision == "fp64" else torch.float32
+    dev = seg_of.device
+    n = seg_of.shape[0]
+    if out is None:
+        out = torch.empty(total_elems, dtype=odt, device=dev)
+    if out_offset is None:
+        out_offset = torch.empty(n, dtype=torch.int64, device=dev)
+    if workspace is None:
+        workspace = torch.empty(coffee_batch_workspace_size(len(segments), n), dtype=torch.uint8, device=dev)
+    segs, _keep = _segments(segments)
+    st = _lib.coffee_assemble_batch_packed(PRECISIONS[precision], segs, len(segments),
+                                           _dptr(seg_of, torch.int32, "seg_of"),
+                                           _dptr(cell_of, torch.int64, "cell_of"), n, _dptr(out, odt, "out"),
+                                           _dptr(out_offset, torch.int64, "out_offset"),
+                                           workspace.data_ptr(), workspace.numel(), _stream(stream))
+    _check(st, "coffee_assemble_batch_packed")
+    return out, out_offset
 
 
 def coffee_check_geometry(cell, coords, cell_to_vertex, stream=None) -> int:

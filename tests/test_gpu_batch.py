@@ -129,3 +129,88 @@ def test_batch_validation(cf):
     with pytest.raises(cf.CoffeeError) as ei:
         cf.coffee_assemble_batch(segs, seg_of, cell_of, offs, mb.total_elems, workspace=small)
     assert ei.value.code == 3
+
+
+def packed_offsets(mb):
+    """The packed layout from its definition: segments in order, each segment's
+    entries in increasing entry index, tensors back to back."""
+    nn = np.array([I.n_scalar_dofs(d, p) ** 2 for (_, d, p) in mb.segments], dtype=np.int64)
+    off = np.empty(mb.seg_of.shape[0], dtype=np.int64)
+    pos = 0
+    for b in range(len(mb.segments)):
+        idx = np.nonzero(mb.seg_of == b)[0]
+        off[idx] = pos + nn[b] * np.arange(idx.size, dtype=np.int64)
+        pos += nn[b] * idx.size
+    return off, int(pos)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("task_cells", [64, 256, 1024])
+def test_packed_batch_layout_and_values(cf, precision, task_cells):
+    """coffee_assemble_batch_packed: the returned offsets are the packed layout
+    exactly, every tensor equals the per-bin launch bit for bit, and a second
+    call reproduces the offsets."""
+    import torch
+    mb = I.mixed_batch(n_tri=24, n_tet=6, tri_counts=(400, 300, 200, 100), tet_counts=(500, 300, 200), seed=7)
+    segs, (seg_of, cell_of, _) = device_batch(cf, mb, 0, task_cells)
+    exp_off, total = packed_offsets(mb)
+    assert total == mb.total_elems
+    got, off = cf.coffee_assemble_batch_packed(segs, seg_of, cell_of, total, precision=precision)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(off.cpu().numpy(), exp_off)
+    ref_scattered = per_bin_reference(cf, mb, segs, precision)  # tensors at mb.out_offset
+    nn = np.array([I.n_scalar_dofs(d, p) ** 2 for (_, d, p) in mb.segments], dtype=np.int64)[mb.seg_of]
+    g = got.cpu().numpy()
+    for i in range(0, mb.seg_of.shape[0], 7):
+        np.testing.assert_array_equal(g[exp_off[i]:exp_off[i] + nn[i]],
+                                      ref_scattered[mb.out_offset[i]:mb.out_offset[i] + nn[i]])
+    _, off2 = cf.coffee_assemble_batch_packed(segs, seg_of, cell_of, total, precision=precision)
+    np.testing.assert_array_equal(off2.cpu().numpy(), exp_off)
+
+
+def test_packed_batch_edge_cases(cf, oracle):
+    """One entry; segments with no entries; counts that are not multiples of a
+    task or of 16; against the oracle."""
+    import torch
+    from gpu_util import TOL
+    for counts in [((1, 0, 0, 0), (0, 0, 0)), ((0, 17, 0, 3), (0, 0, 33)), ((65, 1, 129, 15), (1, 64, 7))]:
+        mb = I.mixed_batch(n_tri=12, n_tet=4, tri_counts=counts[0], tet_counts=counts[1], seed=11)
+        segs, (seg_of, cell_of, _) = device_batch(cf, mb, 0, 64)
+        exp_off, total = packed_offsets(mb)
+        got, off = cf.coffee_assemble_batch_packed(segs, seg_of, cell_of, total, precision="fp32")
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(off.cpu().numpy(), exp_off)
+        g = got.cpu().numpy()
+        for b, (form, d, p) in enumerate(mb.segments):
+            idx = np.nonzero(mb.seg_of == b)[0]
+            if idx.size == 0:
+                continue
+            mesh, f = (mb.tri, mb.f_tri) if d == 2 else (mb.tet, mb.f_tet)
+            ref = oracle.assemble(form, mesh, p, fields=[f], cells=mb.cell_of[idx]).reshape(idx.size, -1)
+            gg = np.stack([g[exp_off[i]:exp_off[i] + ref.shape[1]] for i in idx]).astype(np.float64)
+            err = np.max(np.max(np.abs(gg - ref), 1) / np.max(np.abs(ref), 1))
+            assert err < TOL["fp32"], (counts, form, d, p, err)
+
+
+def test_packed_batch_full_size_sampled(cf):
+    """The 3,000,000-entry mixed batch in the packed layout: offsets equal the
+    layout's definition; sampled entries equal per-bin launches bit for bit."""
+    import torch
+    mb = I.mixed_batch()
+    segs, (seg_of, cell_of, _) = device_batch(cf, mb)
+    exp_off, total = packed_offsets(mb)
+    got, off = cf.coffee_assemble_batch_packed(segs, seg_of, cell_of, total, precision="fp32")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(off.cpu().numpy(), exp_off)
+    rng = np.random.default_rng(1)
+    for b, (form, d, p) in enumerate(mb.segments):
+        idx = np.nonzero(mb.seg_of == b)[0]
+        pick = np.sort(rng.choice(idx, size=min(200, idx.size), replace=False))
+        sg = segs[b]
+        cells = torch.as_tensor(mb.cell_of[pick], device=sg.coords.device)
+        sub_f = cf.DeviceField(sg.coeff.values, sg.coeff.cell_to_dof[cells].contiguous(), 1, 1)
+        A = cf.coffee_assemble(form, d, p, sg.coords, sg.cell_to_vertex[cells].contiguous(), coeffs=[sub_f],
+                               precision="fp32").reshape(len(pick), -1)
+        nn = A.shape[1]
+        gidx = torch.as_tensor((exp_off[pick][:, None] + np.arange(nn)[None, :]).reshape(-1), device=got.device)
+        np.testing.assert_array_equal(got[gidx].reshape(len(pick), nn).cpu().numpy(), A.cpu().numpy())
