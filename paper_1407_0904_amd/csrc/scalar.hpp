@@ -132,7 +132,8 @@ __device__ inline void scalar_tile(const LinArgs& A, ScalarWave<FORM, D, P, FD, 
                 out_t* dst = W.out + c0 * NN;
                 u32x4* d4p = reinterpret_cast<u32x4*>(dst);
                 if constexpr (FULL) {
-                    // all LDS reads first, then the stores
+                    // all LDS reads first, then the stores (nontemporal: the
+                    // element tensors are not read again by this kernel)
                     constexpr int NV = 8 * NN / PER16;
                     constexpr int PL = (NV + 63) / 64;
                     u32x4 tmp[PL];
@@ -142,7 +143,7 @@ __device__ inline void scalar_tile(const LinArgs& A, ScalarWave<FORM, D, P, FD, 
 #pragma unroll
                     for (int i = 0; i < PL; ++i)
                         if (i * 64 + lane < NV) {
-                            d4p[i * 64 + lane] = tmp[i];
+                            __builtin_nontemporal_store(tmp[i], &d4p[i * 64 + lane]);
                         }
                     if constexpr (NV * PER16 != 8 * NN) {
                         constexpr int REM = 8 * NN - NV * PER16;  // < PER16 elements
