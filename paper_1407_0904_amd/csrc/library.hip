@@ -119,7 +119,10 @@ static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym, 
                     }
                 }
     } else {
-        const int KE = 3 * KR, KS = (KE + 31) / 32;
+        // symmetric engine: k' = part KR + k, parts (R_hi, R_lo, R_hi) against
+        // G's (hi, hi, lo); vector engine: k' = 4 k + slot, slots (R_hi, R_lo,
+        // R_hi, 0) against (hi, hi, lo, 0)
+        const int KE = (sym ? 3 : 4) * KR, KS = (KE + 31) / 32;
         buf.assign((size_t)NT * KS * 64 * 16, 0);
         for (int t = 0; t < NT; ++t)
             for (int s = 0; s < KS; ++s)
@@ -127,8 +130,8 @@ static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym, 
                     for (int jj = 0; jj < 8; ++jj) {
                         const int kp = 32 * s + 8 * (l / 16) + jj, c = 16 * t + l % 16;
                         uint16_t h = 0;
-                        if (kp < KE && c < NC && colmap[c] >= 0) {
-                            const int k = kp % KR, part = kp / KR;  // 0: R_hi, 1: R_lo, 2: R_hi
+                        const int k = sym ? kp % KR : kp / 4, part = sym ? kp / KR : kp % 4;
+                        if (kp < KE && c < NC && colmap[c] >= 0 && part < 3) {
                             const float x = (float)R.R[(size_t)k * NN + colmap[c]];
                             const uint16_t hi = bf16_bits_host(x);
                             h = part == 1 ? bf16_bits_host(x - bf16_float_host(hi)) : hi;

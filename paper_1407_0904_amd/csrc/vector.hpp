@@ -45,6 +45,17 @@ __host__ __device__ constexpr int vec_group_tiles(int form, int prec) {
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// K steps and G row length of the vector engine. BF16X3 uses four k slots per
+// G entry, (G_hi, G_hi, G_lo, 0) against (R_hi, R_lo, R_hi, 0), so that an
+// entry is one aligned 8-byte LDS store and the zero leading steps of the
+// off-diagonal Burgers blocks can still be skipped.
+__host__ __device__ constexpr int vec_ksteps(int form, int d, int fd, int prec) {
+    return prec == PREC_BF16X3 ? (4 * kref(form, d, fd) + 31) / 32 : ksteps(form, d, fd, prec);
+}
+__host__ __device__ constexpr int vec_row(int form, int d, int fd, int prec) {
+    return prec == PREC_BF16X3 ? vec_ksteps(form, d, fd, prec) * 32 + 8 : vec_ksteps(form, d, fd, prec) * 4 + 1;
+}
+
 // Coefficient dofs per lane group, fields per dof, components per field.
 template <int FORM, int D, int FD>
 struct VLane {
@@ -65,9 +76,9 @@ struct VecCfg {
     static constexpr int NC = D;
     static constexpr int N = NC * NS;
     static constexpr int KR = kref(FORM, D, FD);
-    static constexpr int KS = ksteps(FORM, D, FD, PREC);
+    static constexpr int KS = vec_ksteps(FORM, D, FD, PREC);
     static constexpr int NT = ntiles(D, P);
-    static constexpr int ROW = GLayout<FORM, D, FD, PREC>::ROW;
+    static constexpr int ROW = vec_row(FORM, D, FD, PREC);
     static constexpr int NF = VLane<FORM, D, FD>::NF;
     static constexpr int RPL = VLane<FORM, D, FD>::RPL;
     static constexpr int TB = vec_group_tiles(FORM, PREC);
@@ -91,15 +102,17 @@ struct VecCfg {
     static constexpr int SLOT = RGMAX * N;  // values of one cell's row group
     static constexpr int CPP = 16 * SLOT * (int)sizeof(out_t) <= 8192 ? 16 : 4;
     static constexpr int STAGE_BYTES = CPP * SLOT * (int)sizeof(out_t);
-    static constexpr int GBUF_BYTES = 16 * ROW * (int)sizeof(g_t);
     static constexpr int RLDS_BYTES = RLDS ? (RBYTES + 15) / 16 * 16 : 0;
     // merged blocks: the G rows of all NC blocks of a row group are built
     // together and contracted in one k-loop that loads each reference
     // fragment once for the NC blocks (a third of the fragment traffic, and NC
     // times the MFMAs per wait), when the NC G buffers fit the LDS budget
-    static constexpr bool MERGED =
-        RLDS_BYTES + WAVES * ((cmax(STAGE_BYTES, NC * GBUF_BYTES) + 15) / 16 * 16) <= 160 * 1024;
-    static constexpr int WAVE_BYTES = (cmax(STAGE_BYTES, (MERGED ? NC : 1) * GBUF_BYTES) + 15) / 16 * 16;
+    static constexpr int GROW = ROW;  // G row length in LDS
+    static constexpr int wave_bytes(int nblk) {
+        return (cmax(STAGE_BYTES, nblk * 16 * GROW * (int)sizeof(g_t)) + 15) / 16 * 16;
+    }
+    static constexpr bool MERGED = RLDS_BYTES + WAVES * wave_bytes(NC) <= 160 * 1024;
+    static constexpr int WAVE_BYTES = wave_bytes(MERGED ? NC : 1);
     static constexpr int LDS_BYTES = RLDS_BYTES + WAVES * WAVE_BYTES;
     // 16-byte stores need every group's range and the cell stride aligned
     static constexpr int PER16 = 16 / (int)sizeof(out_t);
@@ -118,8 +131,8 @@ struct VecCfg {
 // (structurally zero blocks of the reference products are never contracted).
 template <int FORM, int D, int FD, int PREC>
 __device__ constexpr int vec_kstep_begin(int c1, int c2) {
-    return (FORM == F_BURG && c1 != c2 && PREC != PREC_BF16X3) ? (1 + npair(D) + nfield(D, FD) * D) / kstep(PREC)
-                                                                : 0;
+    constexpr int K0 = 1 + npair(D) + nfield(D, FD) * D;  // first E(r, a) entry
+    return (FORM == F_BURG && c1 != c2) ? (PREC == PREC_BF16X3 ? (4 * K0) / 32 : K0 / kstep(PREC)) : 0;
 }
 
 // ---------------------------------------------------------------- per-lane cell data
@@ -222,7 +235,8 @@ __device__ inline void vcell_from_raw(const VRaw<FORM, D, FD>& rw, VCell<FORM, D
 
 // ---------------------------------------------------------------- G rows
 
-// Entry k of a G row in the precision's layout (BF16X3: [hi | hi | lo]).
+// Entry k of a G row in the precision's layout (BF16X3: slots 4k .. 4k + 3
+// hold hi, hi, lo, 0).
 template <int PREC, int KR>
 __device__ inline void put_g(typename PrecT<PREC>::gtype* row, int k, double v) {
     if constexpr (PREC == PREC_F64) {
@@ -232,9 +246,9 @@ __device__ inline void put_g(typename PrecT<PREC>::gtype* row, int k, double v) 
     } else {
         const float x = (float)v;
         const u16 hi = bf16_bits_rne(x);
-        row[k] = hi;
-        row[KR + k] = hi;
-        row[2 * KR + k] = bf16_bits_rne(x - bf16_to_float(hi));
+        const u16 lo = bf16_bits_rne(x - bf16_to_float(hi));
+        const uint2 w = make_uint2((uint32_t)hi | ((uint32_t)hi << 16), (uint32_t)lo);
+        *reinterpret_cast<uint2*>(row + 4 * k) = w;
     }
 }
 
@@ -255,7 +269,7 @@ template <int FORM, int D, int FD, int PREC, int C1, int C2>
 __device__ inline void vec_put_G(const LinArgs& A, const VCell<FORM, D, FD>& cd, bool valid,
                                  typename PrecT<PREC>::gtype* row, int g) {
     using C = VLane<FORM, D, FD>;
-    constexpr int KR = kref(FORM, D, FD), NF = C::NF, KS = ksteps(FORM, D, FD, PREC);
+    constexpr int KR = kref(FORM, D, FD), NF = C::NF, KS = vec_ksteps(FORM, D, FD, PREC);
     const auto& K = cd.K;
     const auto& M = cd.M;
     const double ad = valid ? cd.ad : 0.0;
@@ -312,7 +326,7 @@ __device__ inline void vec_put_G(const LinArgs& A, const VCell<FORM, D, FD>& cd,
     if (g == 0) {
         if constexpr (PREC == PREC_BF16X3) {
 #pragma unroll
-            for (int k = 3 * KR; k < KS * 32; ++k) row[k] = 0;
+            for (int k = 4 * KR; k < KS * 32; ++k) row[k] = 0;
         } else {
 #pragma unroll
             for (int k = KR; k < KS * 4; ++k) row[k] = 0;
@@ -387,7 +401,7 @@ __device__ inline void vec_blocks(const LinArgs& A, const VecWave<FORM, D, P, FD
     using C = VecCfg<FORM, D, P, FD, PREC>;
     using acc_t = typename C::acc_t;
     using frag_t = typename C::frag_t;
-    constexpr int KS = C::KS, ROW = C::ROW;
+    constexpr int KS = C::KS, ROW = C::GROW;
     constexpr int t0 = C::tile_off(GI), NTG = C::tiles_of(GI);
     // keeps the scheduler from building the G rows of later blocks early
     __builtin_amdgcn_sched_barrier(0);
@@ -426,7 +440,7 @@ template <int FORM, int D, int P, int FD, int PREC, int c, int C2>
 __device__ inline void vec_put_G_all(const LinArgs& A, const VecWave<FORM, D, P, FD, PREC>& W,
                                      const VCell<FORM, D, FD>& cd, bool valid, int lane) {
     using C = VecCfg<FORM, D, P, FD, PREC>;
-    vec_put_G<FORM, D, FD, PREC, c, C2>(A, cd, valid, W.gbuf + C2 * 16 * C::ROW + (lane & 15) * C::ROW, W.g);
+    vec_put_G<FORM, D, FD, PREC, c, C2>(A, cd, valid, W.gbuf + C2 * 16 * C::GROW + (lane & 15) * C::GROW, W.g);
     if constexpr (C2 + 1 < D) vec_put_G_all<FORM, D, P, FD, PREC, c, C2 + 1>(A, W, cd, valid, lane);
 }
 
@@ -439,7 +453,7 @@ __device__ inline void vec_blocks_merged(const LinArgs& A, const VecWave<FORM, D
     using C = VecCfg<FORM, D, P, FD, PREC>;
     using acc_t = typename C::acc_t;
     using frag_t = typename C::frag_t;
-    constexpr int KS = C::KS, ROW = C::ROW, NC = C::NC;
+    constexpr int KS = C::KS, ROW = C::GROW, NC = C::NC;
     constexpr int t0 = C::tile_off(GI), NTG = C::tiles_of(GI);
     __builtin_amdgcn_sched_barrier(0);
     vec_put_G_all<FORM, D, P, FD, PREC, c, 0>(A, W, cd, valid, lane);
@@ -478,7 +492,7 @@ __device__ inline void vec_group(const LinArgs& A, const VecWave<FORM, D, P, FD,
     using acc_t = typename C::acc_t;
     using frag_t = typename C::frag_t;
     using out_t = typename C::out_t;
-    constexpr int NS = C::NS, NN = C::NN, N = C::N, NC = C::NC, KS = C::KS, ROW = C::ROW;
+    constexpr int NS = C::NS, NN = C::NN, N = C::N, NC = C::NC, KS = C::KS, ROW = C::GROW;
     constexpr int a0 = C::row0(GI), a1 = C::row1(GI);
     constexpr int t0 = C::tile_off(GI), NTG = C::tiles_of(GI), NE = (a1 - a0) * NS;
     int lane = W.lane;
