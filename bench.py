@@ -40,7 +40,7 @@ TUNING = os.path.join(ROOT, "paper_1407_0904_amd", "tuning_mi355x.txt")
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by a plain copy of known size (profiles/
 # k_scalar_helmholtz_p2_tet_fp64.md); valid only for the kernel they were taken on.
-TRAFFIC = {("helmholtz_p2_tet", "fp64"): 1421.1e6}
+TRAFFIC = {("helmholtz_p2_tet", "fp64"): 1402.2e6}
 
 WORKLOADS = {
     "helmholtz_p2_tet": "Helmholtz P2 tetrahedra, 64^3 x 6 cells, f P2 ~ U[0.5,1.5], jitter 10%, q = 4",
@@ -389,6 +389,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of the output's byte size (counter calibration)")
     ap.add_argument("--grid-mult", type=int, default=0)
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run only the mixed-batch section and print its JSON (for profiling that kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; runs on more than one GPU are not part of this implementation "
@@ -403,6 +405,9 @@ def main():
     if os.path.exists(TUNING):
         coffee.coffee_load_tuning(TUNING)
     ctx = Ctx(args.steps, args.warmup)
+    if args.only_batch:
+        print(json.dumps(mixed_batch_section(ctx), default=str), flush=True)
+        return
     dev = ctx.dev
     w = inputs.workload(args.workload)
     coords, c2v, fields = ctx.upload(w)
