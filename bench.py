@@ -212,6 +212,16 @@ def measure_forward(ctx, w, prec, sample_n=300, seed=3, tag=None):
             "bound": r["bound"], "frac": r["frac"], "max_cell_rel_err": err}
 
 
+def adjoint_flops_per_cell(w):
+    """Multiply-adds x 2 of the contraction the elasticity adjoint implements:
+    V_k = R_k u_c2, then lam_c1 . V_k, for every entry k and block (c1, c2)."""
+    if w.form != "elasticity":
+        return None
+    d, ns = w.mesh.d, n_scalar(w.mesh.d, w.degree)
+    nf = n_scalar(d, 1) if w.fields else 1
+    return 2.0 * nf * d * d * d * (ns * ns + d * ns)
+
+
 def measure_adjoint(ctx, w, tag):
     torch, cf = ctx.torch, ctx.cf
     coords, c2v, fields = ctx.upload(w)
@@ -233,10 +243,18 @@ def measure_adjoint(ctx, w, tag):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     gbs = nbytes / (per.mean() * 1e-3) / 1e9
-    log(f"{tag} adjoint: {per.mean() * 1e3:.1f} us, {gbs:.0f} GB/s")
+    fpc = adjoint_flops_per_cell(w)
+    extra = {}
+    if fpc is not None:
+        t_b = max(nbytes / (HBM_PEAK_GBS * 1e9), E * fpc / (FLOP_PEAK_TF["fp64"] * 1e12))
+        extra = {"algorithmic_flops": E * fpc, "gflops": E * fpc / (per.mean() * 1e-3) / 1e9,
+                 "bound": "fp64" if E * fpc / (FLOP_PEAK_TF["fp64"] * 1e12) > nbytes / (HBM_PEAK_GBS * 1e9)
+                 else "hbm", "frac": t_b / (per.mean() * 1e-3)}
+    log(f"{tag} adjoint: {per.mean() * 1e3:.1f} us, {gbs:.0f} GB/s"
+        + (f", frac {extra['frac']:.2f} ({extra['bound']})" if extra else ""))
     return {"workload": tag, "form": f"{w.form} adjoint (vertex coords and coefficients)", "cells": E,
             "precision": "fp64", "ms_per_step": ms, "kernel_ms": pct(per), "cells_per_s": E / (ms * 1e-3),
-            "algorithmic_bytes": nbytes, "gbs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+            "algorithmic_bytes": nbytes, "gbs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS, **extra,
             "parity": "tests/test_gpu_adjoint.py, tests/test_gpu_svk.py (oracle complex-step gradient, "
                       "central differences)"}
 

@@ -199,6 +199,163 @@ __global__ __launch_bounds__(256) void k_adjoint_linear(AdjArgs A) {
     }
 }
 
+// Elasticity: the contraction T = lam_c1^T R_k u_c2 factored as
+// V_k = R_k u_c2 (shared by the NC test components c1) and T = lam_c1 . V_k,
+// consumed entry by entry: for k = (r, alpha, beta) and every block (c1, c2)
+// the transpose of G's entry
+//     G = |det J| (mu_r (delta_c1c2 (K K^T)_ab + K[a][c2] K[b][c1]) + lambda_r K[a][c1] K[b][c2])
+// (the same arithmetic as reverse_G in linear.hpp, per entry instead of per
+// block). lam_e stays in registers, u_e rows are re-read per dof r (L1), R is
+// read from LDS with wave-uniform addresses. Per cell: NF D^2 NC (NS^2 +
+// NC NS) multiply-adds for the values (14k for P2 tetrahedra, against 32k for
+// the per-block contraction), and the dof r's coefficient bars are added to
+// the global gradients as soon as its loop ends.
+template <int D, typename T>
+__device__ inline T sel_rt(const T* x, int n, int r) {
+    T v = T(0);
+    for (int j = 0; j < n; ++j) v += (r == j ? T(1) : T(0)) * x[j];
+    return v;
+}
+
+template <int D, int P, int FD>
+__global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
+    constexpr int NS = nsc(D, P), NN = NS * NS, NC = D, N = NC * NS;
+    constexpr int NF = nfield(D, FD), KR = NF * D * D;
+    __shared__ double sR[KR * NN];
+    for (int i = threadIdx.x; i < KR * NN; i += blockDim.x) sR[i] = A.R[i];
+    __syncthreads();
+    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.L.ncells;
+         cell += (int64_t)gridDim.x * blockDim.x) {
+        CellIdx<F_ELAST, D, FD> ix;
+        CellRaw<F_ELAST, D, FD> raw;
+        load_idx<F_ELAST, D, FD>(A.L, cell, ix);
+        load_raw<F_ELAST, D, FD>(A.L, cell, ix, raw);
+        CellData<F_ELAST, D, FD, double> cd;
+        cell_from_raw<F_ELAST, D, FD>(raw, cd);
+        const auto& K = cd.g.K;
+        const double ad = cd.g.adet;
+        const double* lam_e = A.lam + cell * N;
+        const double* u_e = A.u + cell * N;
+        double lam[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) lam[i] = lam_e[i];
+        double S = 0.0, Kbar[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Kbar[i][j] = 0.0;
+#pragma unroll 1
+        for (int r = 0; r < NF; ++r) {
+            const double mu = FD > 0 ? sel_rt<D>(cd.f0, NF, r) : A.L.c0;
+            const double lm = FD > 0 ? sel_rt<D>(cd.f1, NF, r) : A.L.c1;
+            double mub = 0.0, lmb = 0.0;
+#pragma unroll
+            for (int c2 = 0; c2 < NC; ++c2) {
+                double u[NS];
+#pragma unroll
+                for (int b = 0; b < NS; ++b) u[b] = u_e[c2 * NS + b];
+                // (alpha, beta) in a rolled loop; the rows K[alpha][.] and
+                // K[beta][.] are picked arithmetically and the Kbar updates of
+                // the two rows collected in xa, xb and added back the same way
+#pragma unroll 1
+                for (int ab = 0; ab < D * D; ++ab) {
+                    const int al = ab / D, be = ab - (ab / D) * D;
+                    double Ka[D], Kb[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        double x = 0.0, y = 0.0;
+#pragma unroll
+                        for (int row = 0; row < D; ++row) {
+                            x += (row == al ? 1.0 : 0.0) * K[row][i];
+                            y += (row == be ? 1.0 : 0.0) * K[row][i];
+                        }
+                        Ka[i] = x;
+                        Kb[i] = y;
+                    }
+                    const double* Rk = sR + (r * D * D + ab) * NN;
+                    double V[NS];
+#pragma unroll
+                    for (int a = 0; a < NS; ++a) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int b = 0; b < NS; ++b) v += Rk[a * NS + b] * u[b];
+                        V[a] = v;
+                    }
+                    double kk = 0.0;  // (K K^T)_{alpha beta}
+#pragma unroll
+                    for (int i = 0; i < D; ++i) kk += Ka[i] * Kb[i];
+                    double xa[D], xb[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) xa[i] = xb[i] = 0.0;
+#pragma unroll
+                    for (int c1 = 0; c1 < NC; ++c1) {
+                        double g = 0.0;
+#pragma unroll
+                        for (int a = 0; a < NS; ++a) g += lam[c1 * NS + a] * V[a];
+                        const double gb = ad * g;
+                        mub += gb * ((c1 == c2 ? kk : 0.0) + Ka[c2] * Kb[c1]);
+                        lmb += gb * Ka[c1] * Kb[c2];
+                        const double gm = gb * mu, gl = gb * lm;
+                        if (c1 == c2) {
+#pragma unroll
+                            for (int i = 0; i < D; ++i) {
+                                xa[i] += gm * Kb[i];
+                                xb[i] += gm * Ka[i];
+                            }
+                        }
+                        xa[c2] += gm * Kb[c1];
+                        xb[c1] += gm * Ka[c2];
+                        xa[c1] += gl * Kb[c2];
+                        xb[c2] += gl * Ka[c1];
+                    }
+#pragma unroll
+                    for (int row = 0; row < D; ++row) {
+                        const double wa = row == al ? 1.0 : 0.0, wb = row == be ? 1.0 : 0.0;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) Kbar[row][i] += wa * xa[i] + wb * xb[i];
+                    }
+                }
+            }
+            S += mu * mub + lm * lmb;
+            if constexpr (FD > 0) {
+                if (A.grad_f0) {
+                    const int64_t i0 = A.L.f0.map ? (int64_t)A.L.f0.map[cell * NF + r] : cell * NF + r;
+                    atomicAdd(A.grad_f0 + i0, A.seed * mub);
+                }
+                if (A.grad_f1) {
+                    const int64_t i1 = A.L.f1.map ? (int64_t)A.L.f1.map[cell * NF + r] : cell * NF + r;
+                    atomicAdd(A.grad_f1 + i1, A.seed * lmb);
+                }
+            }
+        }
+        if (A.cell_value) A.cell_value[cell] = S;
+        // chain to the coordinates (as in k_adjoint_linear)
+        double Jbar[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                double t = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) t += K[a][i] * Kbar[a][b] * K[j][b];
+                Jbar[i][j] = -t + S * K[j][i];
+            }
+        const double sd = A.seed;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double x0 = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                atomicAdd(A.grad_coords + (int64_t)ix.v[j + 1] * D + i, sd * Jbar[i][j]);
+                x0 -= Jbar[i][j];
+            }
+            atomicAdd(A.grad_coords + (int64_t)ix.v[0] * D + i, sd * x0);
+        }
+    }
+}
+
 }  // namespace dev
 
 typedef hipError_t (*AdjLaunch)(const dev::AdjArgs&, hipStream_t, int grid);
@@ -207,9 +364,13 @@ struct AdjEntry {
     AdjLaunch launch;
 };
 
+// Elasticity uses the factored kernel when its reference tensor fits in LDS.
 template <int FORM, int D, int P, int FD>
 hipError_t launch_adjoint(const dev::AdjArgs& a, hipStream_t s, int grid) {
-    hipLaunchKernelGGL((dev::k_adjoint_linear<FORM, D, P, FD>), dim3(grid), dim3(256), 0, s, a);
+    if constexpr (FORM == dev::F_ELAST && dev::adj_r_in_lds<FORM, D, P, FD>())
+        hipLaunchKernelGGL((dev::k_adjoint_elast<D, P, FD>), dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((dev::k_adjoint_linear<FORM, D, P, FD>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
