@@ -34,7 +34,8 @@ namespace coffee {
 namespace dev {
 
 constexpr int kMaxBins = 16;
-constexpr int kMaxSlices = 1024;
+constexpr int kMaxSlices = 4096;
+constexpr int kScanThreads = 1024;  // k_bin_scan: kMaxSlices / kScanThreads slices per thread
 
 struct BinDesc {
     const double* coords;
@@ -80,40 +81,39 @@ __global__ __launch_bounds__(256) void k_bin_count(BatchArgs A) {
     for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) atomicAdd(&h[A.seg_of[i]], 1u);
     __syncthreads();
     if (threadIdx.x < kMaxBins) A.scnt[blockIdx.x * kMaxBins + threadIdx.x] = h[threadIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.queue[0] = 0;  // task queue of k_batch
 }
 
-// One workgroup of kMaxSlices threads: for each bin an exclusive scan of the
-// per-slice counts (each slice's first position inside its bin), then the bin
-// totals, first positions and (packed layout) first elements.
-__global__ __launch_bounds__(kMaxSlices) void k_bin_scan(BatchArgs A) {
-    __shared__ unsigned int sc[kMaxSlices];
-    __shared__ unsigned long long tot[kMaxBins];
-    const int t = threadIdx.x;
-    for (int b = 0; b < A.nbins; ++b) {
-        const unsigned int v = t < A.nslices ? A.scnt[t * kMaxBins + b] : 0u;
-        sc[t] = v;
+// One workgroup per bin: an exclusive scan of the bin's per-slice counts (each
+// slice's first position inside its bin; every thread takes consecutive
+// slices), and the bin's total.
+__global__ __launch_bounds__(kScanThreads) void k_bin_scan(BatchArgs A) {
+    constexpr int PER = kMaxSlices / kScanThreads;
+    __shared__ unsigned int sc[kScanThreads];
+    const int t = threadIdx.x, b = blockIdx.x;
+    unsigned int v[PER], sum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int sl = t * PER + j;
+        v[j] = sl < A.nslices ? A.scnt[sl * kMaxBins + b] : 0u;
+        sum += v[j];
+    }
+    sc[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const unsigned int x = t >= d ? sc[t - d] : 0u;
         __syncthreads();
-        for (int d = 1; d < kMaxSlices; d <<= 1) {
-            const unsigned int x = t >= d ? sc[t - d] : 0u;
-            __syncthreads();
-            sc[t] += x;
-            __syncthreads();
-        }
-        if (t < A.nslices) A.scnt[t * kMaxBins + b] = sc[t] - v;  // exclusive
-        if (t == kMaxSlices - 1) tot[b] = sc[t];
+        sc[t] += x;
         __syncthreads();
     }
-    if (t == 0) {
-        unsigned long long p = 0, e = 0;
-        for (int b = 0; b < A.nbins; ++b) {
-            A.counts[b] = tot[b];
-            A.offs[b] = p;
-            A.ebase[b] = e;
-            p += tot[b];
-            e += tot[b] * (unsigned long long)A.bins[b].nn;
-        }
-        A.queue[0] = 0;
+    unsigned int run = sc[t] - sum;  // exclusive prefix of this thread's slices
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int sl = t * PER + j;
+        if (sl < A.nslices) A.scnt[sl * kMaxBins + b] = run;
+        run += v[j];
     }
+    if (t == kScanThreads - 1) A.counts[b] = sc[t];
 }
 
 // Slice s, in input order, 256 entries at a time: an entry's position in its
@@ -121,12 +121,28 @@ __global__ __launch_bounds__(kMaxSlices) void k_bin_scan(BatchArgs A) {
 // chunks and earlier waves of this chunk, plus its rank among the lanes of its
 // wave with the same bin (ballot).
 __global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A) {
-    __shared__ unsigned long long cur[kMaxBins];
+    __shared__ unsigned long long cur[kMaxBins], offs[kMaxBins], ebase[kMaxBins];
     __shared__ unsigned int wtot[4][kMaxBins];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t s0 = blockIdx.x * A.slice;
     const int64_t s1 = s0 + A.slice < A.nentries ? s0 + A.slice : A.nentries;
-    if (t < A.nbins) cur[t] = A.offs[t] + A.scnt[blockIdx.x * kMaxBins + t];
+    if (t == 0) {
+        // bin totals -> first positions and (packed layout) first elements;
+        // block 0 publishes them for k_batch
+        unsigned long long p = 0, e = 0;
+        for (int b = 0; b < A.nbins; ++b) {
+            offs[b] = p;
+            ebase[b] = e;
+            p += A.counts[b];
+            e += A.counts[b] * (unsigned long long)A.bins[b].nn;
+            if (blockIdx.x == 0) {
+                A.offs[b] = offs[b];
+                A.ebase[b] = ebase[b];
+            }
+        }
+    }
+    __syncthreads();
+    if (t < A.nbins) cur[t] = offs[t] + A.scnt[blockIdx.x * kMaxBins + t];
     __syncthreads();
     const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (int64_t i0 = s0; i0 < s1; i0 += 256) {
@@ -146,7 +162,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A) {
             A.bcell[pos] = (int32_t)A.cell_of[i];
             int64_t off;
             if (A.packed) {
-                off = (int64_t)(A.ebase[b] + (pos - A.offs[b]) * (unsigned long long)A.bins[b].nn);
+                off = (int64_t)(ebase[b] + (pos - offs[b]) * (unsigned long long)A.bins[b].nn);
                 A.out_offset_w[i] = off;
             } else {
                 off = A.out_offset[i];
@@ -540,7 +556,7 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
     hipStream_t s = (hipStream_t)hip_stream;
     const int ncu = num_cu(devid);
     hipLaunchKernelGGL(dev::k_bin_count, dim3(a.nslices), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(dev::k_bin_scan, dim3(1), dim3(dev::kMaxSlices), 0, s, a);
+    hipLaunchKernelGGL(dev::k_bin_scan, dim3(nseg), dim3(dev::kScanThreads), 0, s, a);
     hipLaunchKernelGGL(dev::k_bin_scatter, dim3(a.nslices), dim3(256), 0, s, a);
     stage_elems = (stage_elems + 3) / 4 * 4;  // 16-byte multiple for FP32
     const size_t gsz = esz;
