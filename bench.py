@@ -273,7 +273,7 @@ def mixed_batch_section(ctx):
     tet_v = torch.as_tensor(mb.tet.cells, device=dev)
     f_tri = cf.DeviceField.from_host(mb.f_tri, dev)
     f_tet = cf.DeviceField.from_host(mb.f_tet, dev)
-    costs = tuner.read_batch_costs(TUNING)
+    costs = tuner.read_batch_costs(TUNING, "packed") or tuner.read_batch_costs(TUNING)
     # queue order: costliest bins first (tuned ns per cell, else the tensor size)
     key = lambda b: -costs.get((mb.segments[b][0], mb.segments[b][1], mb.segments[b][2], "fp32"),
                                n_scalar(mb.segments[b][1], mb.segments[b][2]) ** 2 * 1e-3)

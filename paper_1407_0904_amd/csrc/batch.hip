@@ -526,7 +526,8 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
         }
         if (packed) {
             d.variant = 2;
-            if (s.task_cells == 0) d.task_cells = kPackedTaskCells;
+            int pt = 0;
+            if (s.task_cells == 0) d.task_cells = tuned_packed(s.form, s.cell, s.degree, precision, &pt) ? pt : kPackedTaskCells;
         }
         // the packed tiles stage 8 tensors when they fit 16 KiB (the
         // single-form engine's rule), the per-entry staged variant always

@@ -28,6 +28,7 @@ coffee_status get_rtable_public(int dev, int form, int dim, int p, int q, int fd
 int batch_grid_mult();
 int tuned_grid_mult(int form, int cell, int degree, int fd, int prec);
 bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* task_cells);
+bool tuned_packed(int form, int cell, int degree, int prec, int* task_cells);
 void free_svk_tables();
 int num_cu(int dev);
 int blocks_per_cu(int dev, const void* kernel, int threads, int lds_bytes);

@@ -3,7 +3,10 @@
 //
 //   linear <form> <cell> <degree> <field_degree> <precision> <grid_mult>
 //   batch  <form> <cell> <degree> <precision> <variant> <task_cells> <ns_per_cell>
+//   packed <form> <cell> <degree> <precision> <task_cells> <ns_per_cell>
 //
+// (batch: coffee_assemble_batch, caller's layout; packed:
+// coffee_assemble_batch_packed.)
 // '#' starts a comment. The paper weighs a cost model against auto-tuning
 // (section 4) and reports the best over every feasible unroll factor next to
 // the model's pick (section 5.6); here the search is exhaustive over a small
@@ -29,12 +32,13 @@ static std::mutex g_tmu;
 static bool g_loaded = false;
 static std::map<std::tuple<int, int, int, int, int>, int> g_linear;      // -> grid_mult
 static std::map<std::tuple<int, int, int, int>, BatchTune> g_batch;       // (form, cell, degree, prec)
+static std::map<std::tuple<int, int, int, int>, BatchTune> g_packed;      // (form, cell, degree, prec)
 
 static coffee_status parse(const char* path) {
     FILE* f = std::fopen(path, "r");
     if (!f) return COFFEE_E_INVALID_ARG;
     std::map<std::tuple<int, int, int, int, int>, int> lin;
-    std::map<std::tuple<int, int, int, int>, BatchTune> bat;
+    std::map<std::tuple<int, int, int, int>, BatchTune> bat, pk;
     char line[512];
     coffee_status st = COFFEE_OK;
     while (std::fgets(line, sizeof line, f)) {
@@ -62,6 +66,19 @@ static coffee_status parse(const char* path) {
             t.task_cells = tc;
             t.ns_per_cell = ns;
             bat[std::make_tuple(form, cell, deg, prec)] = t;
+        } else if (!std::strcmp(kind, "packed")) {
+            int form, cell, deg, prec, tc;
+            double ns;
+            if (std::sscanf(line, "%*s %d %d %d %d %d %lf", &form, &cell, &deg, &prec, &tc, &ns) != 6 || tc < 64 ||
+                tc > 1024 || tc % 64 != 0) {
+                st = COFFEE_E_INVALID_ARG;
+                break;
+            }
+            BatchTune t;
+            t.variant = 2;
+            t.task_cells = tc;
+            t.ns_per_cell = ns;
+            pk[std::make_tuple(form, cell, deg, prec)] = t;
         } else {
             st = COFFEE_E_INVALID_ARG;
             break;
@@ -71,6 +88,7 @@ static coffee_status parse(const char* path) {
     if (st == COFFEE_OK) {
         g_linear.swap(lin);
         g_batch.swap(bat);
+        g_packed.swap(pk);
     }
     return st;
 }
@@ -99,6 +117,15 @@ bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* ta
     return true;
 }
 
+bool tuned_packed(int form, int cell, int degree, int prec, int* task_cells) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    ensure_loaded();
+    auto it = g_packed.find(std::make_tuple(form, cell, degree, prec));
+    if (it == g_packed.end()) return false;
+    *task_cells = it->second.task_cells;
+    return true;
+}
+
 }  // namespace coffee
 
 extern "C" coffee_status coffee_load_tuning(const char* path) {
@@ -107,6 +134,7 @@ extern "C" coffee_status coffee_load_tuning(const char* path) {
     if (!path) {
         coffee::g_linear.clear();
         coffee::g_batch.clear();
+        coffee::g_packed.clear();
         return COFFEE_OK;
     }
     return coffee::parse(path);

@@ -10,8 +10,9 @@ call. Keys and candidates:
   multiplier (persistent grid of CUs x resident workgroups x m, or one
   workgroup per 256 cells);
 * mixed-batch bins (form, cell, degree, precision): store variant (LDS-staged
-  or direct) x cells per queue task; the measured ns per cell is kept so
-  that callers can order bins by cost.
+  or direct) x cells per queue task for the caller's layout, and cells per
+  queue task for the packed layout; the measured ns per cell is kept so that
+  callers can order bins by cost.
 
 The result is a text cache read by coffee_load_tuning / COFFEE_TUNE_CACHE.
 
@@ -116,6 +117,44 @@ def tune_batch(mb, precision: str = "fp32", variants=(0, 1), task_cells=(128, 25
     return entries
 
 
+def tune_batch_packed(mb, precision: str = "fp32", task_cells=(128, 256, 512, 1024), log=print):
+    """Best cells per task per bin of a mixed batch in the packed layout, timed one bin at a time."""
+    import torch
+    from . import coffee
+    dev = torch.device("cuda:0")
+    tri_c = torch.as_tensor(mb.tri.coords, device=dev)
+    tri_v = torch.as_tensor(mb.tri.cells, device=dev)
+    tet_c = torch.as_tensor(mb.tet.coords, device=dev)
+    tet_v = torch.as_tensor(mb.tet.cells, device=dev)
+    f_tri = coffee.DeviceField.from_host(mb.f_tri, dev)
+    f_tet = coffee.DeviceField.from_host(mb.f_tet, dev)
+    entries = []
+    for b, (form, d, p) in enumerate(mb.segments):
+        idx = np.nonzero(mb.seg_of == b)[0]
+        n = idx.size
+        if n == 0:
+            continue
+        c, v, f = (tri_c, tri_v, f_tri) if d == 2 else (tet_c, tet_v, f_tet)
+        seg_of = torch.zeros(n, dtype=torch.int32, device=dev)
+        cell_of = torch.as_tensor(mb.cell_of[idx], device=dev)
+        size = (p + 1) * (p + 2) // 2 if d == 2 else (p + 1) * (p + 2) * (p + 3) // 6
+        out = torch.empty(n * size * size, dtype=torch.float64 if precision == "fp64" else torch.float32, device=dev)
+        offs = torch.empty(n, dtype=torch.int64, device=dev)
+        ws = torch.empty(coffee.coffee_batch_workspace_size(1, n), dtype=torch.uint8, device=dev)
+        best = None
+        for tc in task_cells:
+            seg = coffee.Segment(form, d, p, c, v, f, task_cells=tc)
+            ms = _time(lambda: coffee.coffee_assemble_batch_packed([seg], seg_of, cell_of, out.numel(),
+                                                                   precision=precision, out=out, out_offset=offs,
+                                                                   workspace=ws))
+            log(f"  packed bin {form} d{d} p{p} {precision} task {tc}: {ms * 1e3:.1f} us ({n} cells)")
+            if best is None or ms < best[1]:
+                best = (tc, ms)
+        entries.append(("packed", FORM_IDS[form], d, p, PREC_IDS[precision], best[0], best[1] * 1e6 / n))
+        del out, offs, ws
+    return entries
+
+
 def write_cache(path: str, entries, header: str = ""):
     with open(path, "w") as f:
         f.write("# coffee tuning cache (written by paper_1407_0904_amd.tuner)\n")
@@ -124,12 +163,15 @@ def write_cache(path: str, entries, header: str = ""):
         for e in entries:
             if e[0] == "linear":
                 f.write("linear %d %d %d %d %d %d\n" % e[1:])
+            elif e[0] == "packed":
+                f.write("packed %d %d %d %d %d %.6f\n" % e[1:])
             else:
                 f.write("batch %d %d %d %d %d %d %.6f\n" % e[1:])
 
 
-def read_batch_costs(path: str):
-    """{(form, cell, degree, precision): ns_per_cell} of a cache file."""
+def read_batch_costs(path: str, kind: str = "batch"):
+    """{(form, cell, degree, precision): ns_per_cell} of a cache file's "batch"
+    (caller's layout) or "packed" lines."""
     costs = {}
     if not path or not os.path.exists(path):
         return costs
@@ -137,9 +179,9 @@ def read_batch_costs(path: str):
     inv_p = {v: k for k, v in PREC_IDS.items()}
     for line in open(path):
         line = line.split("#", 1)[0].split()
-        if line and line[0] == "batch":
+        if line and line[0] == kind:
             form, cell, deg, prec = (int(x) for x in line[1:5])
-            costs[(inv_f[form], cell, deg, inv_p[prec])] = float(line[7])
+            costs[(inv_f[form], cell, deg, inv_p[prec])] = float(line[-1])
     return costs
 
 
@@ -160,6 +202,7 @@ def main(argv=None):
         mb = inputs.mixed_batch(n_tri=64, n_tet=12, tri_counts=(3000, 2000, 1500, 1000),
                                 tet_counts=(3000, 2000, 1000))
     entries += tune_batch(mb, "fp32")
+    entries += tune_batch_packed(mb, "fp32")
     write_cache(args.out, entries, header=f"device {name}")
     coffee.coffee_load_tuning(args.out)
     print(f"wrote {len(entries)} entries to {args.out}")
