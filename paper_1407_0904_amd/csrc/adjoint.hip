@@ -398,7 +398,9 @@ static const std::vector<AdjEntry>& adj_registry() {
 static std::mutex g_adj_mu;
 static std::map<std::tuple<int, int, int, int, int, int>, void*> g_adj_tables;  // (dev, form, dim, p, q, fd)
 
-static coffee_status adjoint_table(int dev, int form, int dim, int p, int q, int fd, const double** out) {
+// FP64 reference tensors [KR][NS * NS] (unpacked), built and uploaded on first
+// use; shared by the adjoint kernels and the degree-1 FMA kernels.
+coffee_status reference_table_f64(int dev, int form, int dim, int p, int q, int fd, const double** out) {
     std::lock_guard<std::mutex> lk(g_adj_mu);
     auto key = std::make_tuple(dev, form, dim, p, q, fd);
     auto it = g_adj_tables.find(key);
@@ -444,7 +446,7 @@ coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, cons
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return COFFEE_E_HIP;
     const double* R = nullptr;
-    coffee_status st = adjoint_table(dev, form, cell, degree, q, fd, &R);
+    coffee_status st = reference_table_f64(dev, form, cell, degree, q, fd, &R);
     if (st != COFFEE_OK) return st;
     dev::AdjArgs a;
     std::memset(&a, 0, sizeof a);

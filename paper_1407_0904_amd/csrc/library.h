@@ -24,6 +24,9 @@ coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, cons
                              double seed, double* grad_coords, double* const* grad_coeff_values,
                              double* cell_value, void* hip_stream);
 void free_adjoint_tables();
+coffee_status reference_table_f64(int dev, int form, int dim, int p, int q, int fd, const double** out);
+coffee_status assemble_p1(int form, int cell, int fd, int q, int precision, const double* coords, const int32_t* c2v,
+                          int64_t ncells, const coffee_field* coeffs, int ncoeff, void* out, void* hip_stream);
 coffee_status get_rtable_public(int dev, int form, int dim, int p, int q, int fd, int prec, const void** out);
 int batch_grid_mult();
 int tuned_grid_mult(int form, int cell, int degree, int fd, int prec);

@@ -299,6 +299,9 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     if (form >= COFFEE_SVK_ENERGY)
         return assemble_svk(form, cell, degree, q, precision, coords, nvert, c2v, ncells, coeffs, constants,
                             nconst, out, hip_stream);
+    // degree 1 mass / Helmholtz: thread-per-cell FMA kernel (p1.hip)
+    if ((form == COFFEE_MASS || form == COFFEE_HELMHOLTZ) && degree == 1 && fd <= 1 && precision != COFFEE_BF16X3)
+        return assemble_p1(form, cell, fd, q, precision, coords, c2v, ncells, coeffs, ncoeff, out, hip_stream);
     const LinEntry* e = find_linear(form, cell, degree, fd, precision);
     if (!e) return COFFEE_E_UNSUPPORTED;
     if (ncells == 0) return COFFEE_OK;

@@ -187,6 +187,25 @@ def test_edge_cases(cf, oracle):
     assert ei.value.code == 2
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("form,d,fd", [("helmholtz", 2, 1), ("helmholtz", 3, 1), ("mass", 2, 0), ("mass", 3, 1),
+                                       ("helmholtz", 3, 0)])
+def test_p1_ragged_counts(cf, oracle, form, d, fd, prec):
+    """Degree-1 forms (the thread-per-cell kernel in FP64/FP32, the MFMA engine
+    in BF16X3) at counts around a 64-cell wave and a 256-cell workgroup."""
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    rng = np.random.default_rng(40 + d)
+    mesh = I.make_mesh(d, 20 if d == 2 else 5, 0.15, rng)  # 800 / 750 cells
+    f = rng.uniform(0.5, 1.5, size=(mesh.nvert, 1))
+    for n in (1, 63, 64, 65, 255, 257, mesh.ncells):
+        sub = I.Mesh(d, mesh.n, mesh.coords, mesh.cells[:n])
+        flds = [I.Field(f, sub.cells, 1, 1)] if fd else []
+        ref = oracle.assemble(form, sub, 1, fields=flds)
+        got = assemble_gpu(form, sub, 1, flds, precision=prec).cpu().numpy()
+        err = cell_rel_err(got, ref)
+        assert err < TOL[prec], (n, err)
+
+
 def test_full_size_helmholtz_p2_tet_sampled(cf, oracle):
     """The 1,572,864-cell Helmholtz P2 tetrahedron workload in the benchmark's
     launch configuration; sampled cells against the oracle, plus the total
