@@ -18,7 +18,8 @@
 //    tensors at a time) or stored straight from the accumulators; in the
 //    packed layout the library places each bin's tensors contiguously, in
 //    input order, and the tile code of the single-form engine writes them as
-//    whole contiguous 16-byte stores.
+//    whole contiguous 16-byte stores. Degree-1 bins run the single-form
+//    degree-1 arithmetic instead (one lane per entry, no MFMA).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,6 +28,7 @@
 #include <vector>
 
 #include "library.h"
+#include "p1.hpp"
 #include "registry.h"
 #include "tables.h"
 
@@ -42,6 +44,7 @@ struct BinDesc {
     const int32_t* c2v;
     FieldArg f0;
     const void* rfrag;
+    const double* r64;  // degree-1 bins: the FP64 reference tensor [K][n*n]
     int type;        // 7 * form + shape, shape in tri P1..P4, tet P1..P3
     int variant;     // 0 staged stores, 1 direct stores, 2 packed (contiguous)
     int task_cells;  // multiple of 64
@@ -68,6 +71,7 @@ struct BatchArgs {
     unsigned int* scnt;           // [kMaxSlices][kMaxBins] per-slice counts, then bases
     int64_t* boff;                // [nentries] output offsets in bin order
     int32_t* bcell;               // [nentries] cell indices in bin order
+    BatchArgs* self;              // copy of these arguments in global memory
 };
 
 // ---------------------------------------------------------------- binning
@@ -81,7 +85,14 @@ __global__ __launch_bounds__(256) void k_bin_count(BatchArgs A) {
     for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) atomicAdd(&h[A.seg_of[i]], 1u);
     __syncthreads();
     if (threadIdx.x < kMaxBins) A.scnt[blockIdx.x * kMaxBins + threadIdx.x] = h[threadIdx.x];
-    if (blockIdx.x == 0 && threadIdx.x == 0) A.queue[0] = 0;  // task queue of k_batch
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) A.queue[0] = 0;  // task queue of k_batch
+        // k_batch reads its arguments from this copy through wave-uniform
+        // pointers instead of a per-lane copy of the kernel argument
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&A);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(A.self);
+        for (int i = threadIdx.x; i < (int)(sizeof(BatchArgs) / 4); i += blockDim.x) dst[i] = src[i];
+    }
 }
 
 // One workgroup per bin: an exclusive scan of the bin's per-slice counts (each
@@ -178,6 +189,26 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A) {
 // ---------------------------------------------------------------- tasks
 
 constexpr int kGtileRow = 16;  // >= any G row of the compiled bin types (KR <= 10)
+constexpr int kSoffs = 64;     // output offsets per wave in LDS (one per lane)
+
+// k_batch's dynamic LDS, named at file scope so that the (non-inlined) task
+// functions address it as LDS. Per wave: G tile (16 x kGtileRow), output
+// offsets (kSoffs), then the staging area.
+extern __shared__ __attribute__((aligned(16))) unsigned char batch_lds[];
+
+template <int PREC>
+struct WaveLds {
+    using g_t = typename PrecT<PREC>::gtype;
+    using out_t = typename PrecT<PREC>::otype;
+    static constexpr unsigned GT_BYTES = 16 * kGtileRow * sizeof(g_t);
+    g_t* gtile;
+    int64_t* soffs;
+    out_t* stage;
+    __device__ explicit WaveLds(unsigned wave_off)
+        : gtile(reinterpret_cast<g_t*>(batch_lds + wave_off)),
+          soffs(reinterpret_cast<int64_t*>(batch_lds + wave_off + GT_BYTES)),
+          stage(reinterpret_cast<out_t*>(batch_lds + wave_off + GT_BYTES + kSoffs * sizeof(int64_t))) {}
+};
 
 // Contract one 16-entry tile (rows j of the current group) and store each
 // entry's tensor at its own offset. FULL: all 64 entries of the group exist,
@@ -221,7 +252,7 @@ __device__ inline void batch_tile(ScalarWave<FORM, D, P, FD, PREC>& W, const dou
                 if (k < TOT) {
                     const int c = k / NN, e = k - (k / NN) * NN;
                     const int64_t o = soffs[c];
-                    if (FULL || o >= 0) W.out[o + e] = W.stage[k];
+                    if (FULL || o >= 0) gstore(&W.out[o + e], W.stage[k]);
                 }
             }
         }
@@ -243,8 +274,8 @@ __device__ inline void batch_tile(ScalarWave<FORM, D, P, FD, PREC>& W, const dou
             for (int v = 0; v < 4; ++v) {
                 if (rok[v]) {
                     const out_t x = (out_t)acc[t][v];
-                    W.out[roff[v] + a * NS + bb] = x;
-                    W.out[roff[v] + bb * NS + a] = x;
+                    gstore(&W.out[roff[v] + a * NS + bb], x);
+                    gstore(&W.out[roff[v] + bb * NS + a], x);
                 }
             }
         }
@@ -252,21 +283,64 @@ __device__ inline void batch_tile(ScalarWave<FORM, D, P, FD, PREC>& W, const dou
     wave_sync();
 }
 
+// What a task function reads of the batch arguments, loaded once through the
+// scalar path (the arguments and descriptors are wave-uniform and no kernel of
+// the batch writes them after k_bin_count).
+struct TaskView {
+    const int32_t* bcell;
+    const int64_t* boff;
+    void* out;
+    int64_t offs, ebase, count;  // of this task's bin
+    LinArgs L;                   // the bin's mesh and field
+    const void* rfrag;
+    const double* r64;
+};
+
+__device__ inline TaskView task_view(const BatchArgs* Ap, const BinDesc* bdp, int bin) {
+    const BatchArgs* A = uniform_ptr(Ap);
+    const BinDesc* bd = uniform_ptr(bdp);
+    TaskView v;
+    v.bcell = cload(&A->bcell);
+    v.boff = cload(&A->boff);
+    v.out = cload(&A->out);
+    v.offs = (int64_t)gload(cload(&A->offs) + bin);
+    v.ebase = (int64_t)gload(cload(&A->ebase) + bin);
+    v.count = (int64_t)gload(cload(&A->counts) + bin);
+    v.L.coords = cload(&bd->coords);
+    v.L.c2v = cload(&bd->c2v);
+    v.L.f0 = FieldArg{cload(&bd->f0.values), cload(&bd->f0.map)};
+    v.L.f1 = FieldArg{nullptr, nullptr};
+    v.L.c0 = 0.0;
+    v.L.c1 = 0.0;
+    v.L.ncells = 0;
+    v.rfrag = cload(&bd->rfrag);
+    v.r64 = cload(&bd->r64);
+    return v;
+}
+
 // n binned entries first .. first + n - 1 of one bin, 64 per group. Not
 // inlined: each bin type is then register-allocated on its own instead of
-// as one body holding every type's live values (which spilled heavily).
+// as one body holding every type's live values (which spilled heavily). The
+// arguments are wave-uniform; the LDS areas are re-derived as LDS pointers
+// (a non-inlined function sees generic pointers).
 template <int FORM, int D, int P, int FD, int PREC, int VARIANT>
-__device__ __attribute__((noinline)) void batch_task(const BatchArgs& A, const BinDesc& bd, int bin, int64_t first, int n, int lane,
-                           typename PrecT<PREC>::gtype* gtile, typename PrecT<PREC>::otype* stage, int64_t* soffs) {
+__device__ __attribute__((noinline)) void batch_task(const BatchArgs* Ap, const BinDesc* bdp, int bin, int64_t first,
+                                                     int n, int lane, unsigned wave_off) {
     using C = ScalarCfg<FORM, D, P, FD, PREC>;
     constexpr int KR = C::KR, NT = C::NT, KS = C::KS, NS = C::NS;
+    bin = __builtin_amdgcn_readfirstlane(bin);
+    n = __builtin_amdgcn_readfirstlane(n);
+    first = uniform_i64(first);
+    const WaveLds<PREC> M(__builtin_amdgcn_readfirstlane(wave_off));
+    int64_t* soffs = M.soffs;
+    const TaskView V = task_view(Ap, bdp, bin);
     ScalarWave<FORM, D, P, FD, PREC> W;
     W.lane = lane;
     W.col = lane & 15;
-    W.gtile = gtile;
-    W.stage = stage;
-    W.rf = reinterpret_cast<const typename C::frag_t*>(bd.rfrag);
-    W.out = reinterpret_cast<typename C::out_t*>(A.out);
+    W.gtile = M.gtile;
+    W.stage = M.stage;
+    W.rf = reinterpret_cast<const typename C::frag_t*>(V.rfrag);
+    W.out = reinterpret_cast<typename C::out_t*>(V.out);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         int u = t * 16 + W.col, a = 0;
@@ -278,13 +352,9 @@ __device__ __attribute__((noinline)) void batch_task(const BatchArgs& A, const B
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int s = 0; s < KS; ++s) W.rreg[t][s] = W.rf[(t * KS + s) * 64 + lane];
+            for (int s = 0; s < KS; ++s) W.rreg[t][s] = gload(W.rf + (t * KS + s) * 64 + lane);
     }
-    LinArgs L;
-    L.coords = bd.coords;
-    L.c2v = bd.c2v;
-    L.f0 = bd.f0;
-    L.f1 = FieldArg{nullptr, nullptr};
+    LinArgs L = V.L;
     const int nfull = n >> 6, ng = (n + 63) >> 6;
     const int64_t last = first + n - 1;
     // binned position of this lane's entry in group g (clamped into the task)
@@ -300,18 +370,18 @@ __device__ __attribute__((noinline)) void batch_task(const BatchArgs& A, const B
     int64_t o0, o1, o2;
     {
         const int64_t p0 = at(0);
-        const int c0 = A.bcell[p0];
-        o0 = A.boff[p0];
+        const int c0 = gload(V.bcell + p0);
+        o0 = gload(V.boff + p0);
         load_idx<FORM, D, FD>(L, c0, ix);
         load_raw<FORM, D, FD>(L, c0, ix, raw);
         G_from_raw<FORM, D, FD>(raw, L, true, Gv);
         const int64_t p1 = at(1);
-        c1 = A.bcell[p1];
-        o1 = A.boff[p1];
+        c1 = gload(V.bcell + p1);
+        o1 = gload(V.boff + p1);
         load_idx<FORM, D, FD>(L, c1, ix);
         const int64_t p2 = at(2);
-        c2 = A.bcell[p2];
-        o2 = A.boff[p2];
+        c2 = gload(V.bcell + p2);
+        o2 = gload(V.boff + p2);
     }
     // Complete the prologue's loads before the first store (one in-order
     // counter covers loads and stores).
@@ -328,17 +398,17 @@ __device__ __attribute__((noinline)) void batch_task(const BatchArgs& A, const B
     asm volatile("" ::"v"(c2), "v"(o1), "v"(o2));
     // packed layout: the bin's tensors are contiguous from out + ebase[bin]
     // in binned order, so entry p of the bin is local cell p of that range
-    const int64_t local0 = first - (int64_t)A.offs[bin];
+    const int64_t local0 = first - V.offs;
     if constexpr (VARIANT == 2) {
-        W.out += A.ebase[bin];
-        L.ncells = (int64_t)A.counts[bin];
+        W.out += V.ebase;
+        L.ncells = V.count;
     }
     for (int g = 0; g < nfull; ++g) {
         load_raw<FORM, D, FD>(L, c1, ix, raw);  // group g + 1
         load_idx<FORM, D, FD>(L, c2, ix);       // group g + 2
         const int64_t p3 = at(g + 3);
-        const int c3 = A.bcell[p3];
-        const int64_t o3 = A.boff[p3];
+        const int c3 = gload(V.bcell + p3);
+        const int64_t o3 = gload(V.boff + p3);
         if constexpr (VARIANT == 2) {
             const int64_t tb = local0 + 64 * (int64_t)g;
             scalar_tile<FORM, D, P, FD, PREC, true>(L, W, Gv, 0, tb);
@@ -376,43 +446,121 @@ __device__ __attribute__((noinline)) void batch_task(const BatchArgs& A, const B
     }
 }
 
+// Degree-1 bins: one lane per entry with the arithmetic of the single-form
+// degree-1 kernel (p1.hpp), 64 entries per group. The tensors go through an
+// LDS row per lane and leave as stores whose lanes cover consecutive elements:
+// of the bin's contiguous range (packed layout) or of each entry's own range
+// (caller's layout, offsets in LDS). The gathers of the next groups are issued
+// before the current group's stores, as in the symmetric tiles.
+template <int FORM, int D, int PREC, int VARIANT>
+__device__ __attribute__((noinline)) void batch_task_p1(const BatchArgs* Ap, const BinDesc* bdp, int bin, int64_t first,
+                                                        int n, int lane, unsigned wave_off) {
+    using out_t = typename PrecT<PREC>::otype;
+    constexpr int FD = 1, NN = (D + 1) * (D + 1), KR = kref(FORM, D, FD), SR = p1_row<D>();
+    bin = __builtin_amdgcn_readfirstlane(bin);
+    n = __builtin_amdgcn_readfirstlane(n);
+    first = uniform_i64(first);
+    const WaveLds<PREC> M(__builtin_amdgcn_readfirstlane(wave_off));
+    out_t* stage = M.stage;
+    int64_t* soffs = M.soffs;
+    const TaskView V = task_view(Ap, bdp, bin);
+    const LinArgs L = V.L;
+    const double* R = V.r64;
+    out_t* out = reinterpret_cast<out_t*>(V.out);
+    if constexpr (VARIANT == 2) out += V.ebase + (first - V.offs) * NN;
+    const int ng = (n + 63) >> 6;
+    const int64_t last = first + n - 1;
+    auto at = [&](int g) -> int64_t {
+        const int gg = g < ng ? g : ng - 1;
+        const int64_t p = first + 64 * (int64_t)gg + lane;
+        return p < last ? p : last;
+    };
+    auto off = [&](int64_t p) -> int64_t { return VARIANT == 2 ? 0 : gload(V.boff + p); };
+    CellIdx<FORM, D, FD> ix;
+    CellRaw<FORM, D, FD> raw;
+    int64_t o0, o1, o2;
+    int c1, c2;
+    {
+        const int64_t p0 = at(0);
+        const int c0 = gload(V.bcell + p0);
+        o0 = off(p0);
+        load_idx<FORM, D, FD>(L, c0, ix);
+        load_raw<FORM, D, FD>(L, c0, ix, raw);
+        const int64_t p1 = at(1);
+        c1 = gload(V.bcell + p1);
+        o1 = off(p1);
+        load_idx<FORM, D, FD>(L, c1, ix);
+        const int64_t p2 = at(2);
+        c2 = gload(V.bcell + p2);
+        o2 = off(p2);
+    }
+    for (int g = 0; g < ng; ++g) {
+        double G[KR];
+        {
+            CellData<FORM, D, FD> cd;
+            cell_from_raw<FORM, D, FD>(raw, cd);
+            build_G<FORM, D, FD, 0, 0>(cd, L, G);
+        }
+        p1_tensor<FORM, D, FD, out_t>(G, R, stage + lane * SR);
+        if constexpr (VARIANT != 2) soffs[lane] = o0;
+        load_raw<FORM, D, FD>(L, c1, ix, raw);  // group g + 1
+        load_idx<FORM, D, FD>(L, c2, ix);       // group g + 2
+        const int64_t p3 = at(g + 3);
+        const int c3 = gload(V.bcell + p3);
+        const int64_t o3 = off(p3);
+        wave_sync();
+        const int m = n - 64 * g < 64 ? n - 64 * g : 64;
+        out_t* dst = out + (int64_t)64 * g * NN;
+#pragma unroll
+        for (int i0 = 0; i0 < 64 * NN; i0 += 64) {
+            const int i = i0 + lane;
+            const int c = i / NN, e = i - (i / NN) * NN;
+            if (c < m) {
+                if constexpr (VARIANT == 2) gstore(&dst[i], stage[c * SR + e]);
+                else gstore(&out[soffs[c] + e], stage[c * SR + e]);
+            }
+        }
+        wave_sync();
+        o0 = o1;
+        o1 = o2;
+        o2 = o3;
+        c1 = c2;
+        c2 = c3;
+    }
+}
+
 template <int PREC, int VARIANT>
-__device__ inline void batch_dispatch_v(const BatchArgs& A, const BinDesc& bd, int bin, int64_t first, int n, int lane,
-                                        typename PrecT<PREC>::gtype* gtile, typename PrecT<PREC>::otype* stage,
-                                        int64_t* soffs) {
-    switch (bd.type) {
-        case 0: batch_task<F_MASS, 2, 1, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 1: batch_task<F_MASS, 2, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 2: batch_task<F_MASS, 2, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 3: batch_task<F_MASS, 2, 4, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 4: batch_task<F_MASS, 3, 1, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 5: batch_task<F_MASS, 3, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 6: batch_task<F_MASS, 3, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 7: batch_task<F_HELM, 2, 1, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 8: batch_task<F_HELM, 2, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 9: batch_task<F_HELM, 2, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 10: batch_task<F_HELM, 2, 4, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 11: batch_task<F_HELM, 3, 1, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 12: batch_task<F_HELM, 3, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
-        case 13: batch_task<F_HELM, 3, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, gtile, stage, soffs); break;
+__device__ inline void batch_dispatch_v(const BatchArgs* A, const BinDesc* bd, int type, int bin, int64_t first,
+                                        int n, int lane, unsigned wave_off) {
+    switch (type) {
+        case 0: batch_task_p1<F_MASS, 2, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 1: batch_task<F_MASS, 2, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 2: batch_task<F_MASS, 2, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 3: batch_task<F_MASS, 2, 4, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 4: batch_task_p1<F_MASS, 3, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 5: batch_task<F_MASS, 3, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 6: batch_task<F_MASS, 3, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 7: batch_task_p1<F_HELM, 2, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 8: batch_task<F_HELM, 2, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 9: batch_task<F_HELM, 2, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 10: batch_task<F_HELM, 2, 4, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 11: batch_task_p1<F_HELM, 3, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 12: batch_task<F_HELM, 3, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 13: batch_task<F_HELM, 3, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
         default: break;
     }
 }
 
-// Dynamic LDS per wave: G tile (16 x kGtileRow), output offsets (8), and the
-// staging area of `stage_elems` elements (8 tensors of the largest staged bin).
+// Dynamic LDS per wave: G tile (16 x kGtileRow), output offsets (kSoffs), and
+// the staging area of `stage_elems` elements (8 tensors of the largest staged
+// bin, or 64 padded degree-1 tensors).
 template <int PREC>
-__global__ __launch_bounds__(256) void k_batch(BatchArgs A, int stage_elems) {
-    using g_t = typename PrecT<PREC>::gtype;
+__global__ __launch_bounds__(256) void k_batch(const BatchArgs* __restrict__ Ap, int stage_elems) {
+    const BatchArgs& A = *Ap;
     using out_t = typename PrecT<PREC>::otype;
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const size_t per_wave = (size_t)16 * kGtileRow * sizeof(g_t) + 8 * sizeof(int64_t) +
-                            (size_t)stage_elems * sizeof(out_t);
-    unsigned char* mine = lds + wave * per_wave;
-    g_t* gtile = reinterpret_cast<g_t*>(mine);
-    int64_t* soffs = reinterpret_cast<int64_t*>(mine + (size_t)16 * kGtileRow * sizeof(g_t));
-    out_t* stage = reinterpret_cast<out_t*>(mine + (size_t)16 * kGtileRow * sizeof(g_t) + 8 * sizeof(int64_t));
+    const unsigned per_wave = WaveLds<PREC>::GT_BYTES + kSoffs * sizeof(int64_t) + (unsigned)stage_elems * sizeof(out_t);
+    const unsigned wave_off = wave * per_wave;
     // tasks per bin from the device counts
     int64_t tstart[kMaxBins + 1];
     tstart[0] = 0;
@@ -426,7 +574,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs A, int stage_elems) {
     for (;;) {
         unsigned long long t = 0;
         if (lane == 0) t = atomicAdd(A.queue, 1ull);
-        t = __shfl(t, 0);
+        t = (unsigned long long)uniform_i64((int64_t)__shfl(t, 0));
         if ((int64_t)t >= total) break;
         int b = 0;
         int64_t tb = 0;
@@ -436,27 +584,30 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs A, int stage_elems) {
                 b = k;
                 tb = tstart[k];
             }
-        const BinDesc& bd = A.bins[b];
-        const int64_t local = ((int64_t)t - tb) * bd.task_cells;
+        const BinDesc* bd = &Ap->bins[b];
+        const int tc = bd->task_cells, type = bd->type, variant = bd->variant;
+        const int64_t local = ((int64_t)t - tb) * tc;
         const int64_t cnt = (int64_t)A.counts[b];
-        const int n = (int)(cnt - local < bd.task_cells ? cnt - local : bd.task_cells);
+        const int n = (int)(cnt - local < tc ? cnt - local : tc);
         const int64_t first = (int64_t)A.offs[b] + local;
-        if (bd.variant == 2) batch_dispatch_v<PREC, 2>(A, bd, b, first, n, lane, gtile, stage, soffs);
-        else if (bd.variant == 0) batch_dispatch_v<PREC, 0>(A, bd, b, first, n, lane, gtile, stage, soffs);
-        else batch_dispatch_v<PREC, 1>(A, bd, b, first, n, lane, gtile, stage, soffs);
+        if (variant == 2) batch_dispatch_v<PREC, 2>(Ap, bd, type, b, first, n, lane, wave_off);
+        else if (variant == 0) batch_dispatch_v<PREC, 0>(Ap, bd, type, b, first, n, lane, wave_off);
+        else batch_dispatch_v<PREC, 1>(Ap, bd, type, b, first, n, lane, wave_off);
     }
 }
 
 }  // namespace dev
 
-// Workspace: header (counts, offs, ebase, queue), per-slice counts, then the
-// binned output offsets and cell indices.
+// Workspace: header (counts, offs, ebase, queue), a copy of the kernel
+// arguments, per-slice counts, then the binned output offsets and cell indices.
 constexpr int64_t kWsHeader = 64 * 8;
+constexpr int64_t kWsArgs = 2048;
 constexpr int64_t kWsSlices = (int64_t)dev::kMaxSlices * dev::kMaxBins * 4;
+static_assert(sizeof(dev::BatchArgs) <= kWsArgs, "batch arguments do not fit the workspace slot");
 
 int64_t batch_workspace_bytes(int nseg, int64_t nentries) {
     (void)nseg;
-    return kWsHeader + kWsSlices + nentries * 12;
+    return kWsHeader + kWsArgs + kWsSlices + nentries * 12;
 }
 
 // Entries per task of the packed layout when the segment leaves it open
@@ -515,6 +666,11 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
         d.c2v = s.cell_to_vertex;
         d.f0 = dev::FieldArg{s.coeff->values, s.coeff->cell_to_dof};
         d.rfrag = rf;
+        d.r64 = nullptr;
+        if (s.degree == 1) {
+            st = reference_table_f64(devid, s.form, s.cell, 1, q, 1, &d.r64);
+            if (st != COFFEE_OK) return st;
+        }
         d.type = type;
         d.nn = ns * ns;
         d.variant = s.variant;
@@ -533,6 +689,7 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
         // single-form engine's rule), the per-entry staged variant always
         const bool stages = packed ? 8 * d.nn * esz <= 16384 : d.variant == 0;
         if (stages) stage_elems = std::max(stage_elems, 8 * d.nn);
+        if (s.degree == 1) stage_elems = std::max(stage_elems, 64 * (d.nn | 1));
     }
     if (nentries == 0) return COFFEE_OK;
     a.nbins = nseg;
@@ -551,8 +708,9 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
     a.offs = ws + dev::kMaxBins;
     a.ebase = ws + 2 * dev::kMaxBins;
     a.queue = ws + 3 * dev::kMaxBins;
-    a.scnt = reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(workspace) + kWsHeader);
-    a.boff = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(workspace) + kWsHeader + kWsSlices);
+    a.self = reinterpret_cast<dev::BatchArgs*>(reinterpret_cast<char*>(workspace) + kWsHeader);
+    a.scnt = reinterpret_cast<unsigned int*>(reinterpret_cast<char*>(workspace) + kWsHeader + kWsArgs);
+    a.boff = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(workspace) + kWsHeader + kWsArgs + kWsSlices);
     a.bcell = reinterpret_cast<int32_t*>(a.boff + nentries);
     hipStream_t s = (hipStream_t)hip_stream;
     const int ncu = num_cu(devid);
@@ -561,7 +719,7 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
     hipLaunchKernelGGL(dev::k_bin_scatter, dim3(a.nslices), dim3(256), 0, s, a);
     stage_elems = (stage_elems + 3) / 4 * 4;  // 16-byte multiple for FP32
     const size_t gsz = esz;
-    const size_t lds = 4 * ((size_t)16 * dev::kGtileRow * gsz + 8 * 8 + (size_t)stage_elems * gsz);
+    const size_t lds = 4 * ((size_t)16 * dev::kGtileRow * gsz + dev::kSoffs * 8 + (size_t)stage_elems * gsz);
     if (lds > 160 * 1024) return COFFEE_E_UNSUPPORTED;
     const void* kern = precision == COFFEE_FP64 ? (const void*)&dev::k_batch<dev::PREC_F64>
                                                 : (const void*)&dev::k_batch<dev::PREC_F32>;
@@ -571,9 +729,11 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, lds) != hipSuccess || nb <= 0) nb = 1;
     const int grid = ncu * nb * std::max(1, batch_grid_mult());
     if (precision == COFFEE_FP64)
-        hipLaunchKernelGGL(dev::k_batch<dev::PREC_F64>, dim3(grid), dim3(256), lds, s, a, stage_elems);
+        hipLaunchKernelGGL(dev::k_batch<dev::PREC_F64>, dim3(grid), dim3(256), lds, s,
+                           (const dev::BatchArgs*)a.self, stage_elems);
     else
-        hipLaunchKernelGGL(dev::k_batch<dev::PREC_F32>, dim3(grid), dim3(256), lds, s, a, stage_elems);
+        hipLaunchKernelGGL(dev::k_batch<dev::PREC_F32>, dim3(grid), dim3(256), lds, s,
+                           (const dev::BatchArgs*)a.self, stage_elems);
     return hipGetLastError() == hipSuccess ? COFFEE_OK : COFFEE_E_HIP;
 }
 

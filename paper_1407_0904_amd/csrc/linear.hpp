@@ -24,6 +24,61 @@
 namespace coffee {
 namespace dev {
 
+// ---------------------------------------------------------------- address spaces
+// Memory accesses that name their address space. A kernel infers the global
+// space for pointers that come from its arguments, but code compiled as a
+// separate (non-inlined) function sees only generic pointers and would use
+// flat instructions, which are slower for LDS and make every wait on an LDS
+// or scalar result also wait for outstanding global loads and stores. The
+// casts are no-ops for pointers that already are global (or LDS).
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ inline T gload(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ inline T gload_nt(const T* p) {
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
+}
+template <typename T>
+__device__ inline void gstore(T* p, T v) {
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+template <typename T>
+__device__ inline void gstore_nt(T* p, T v) {
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T*)p);
+}
+// Load through the scalar (constant) path: for data no kernel writes, at an
+// address that is the same in every lane.
+template <typename T>
+__device__ inline T cload(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+// A wave-uniform pointer held in scalar registers (its value in the first
+// active lane; callers pass one that is the same in every lane).
+template <typename T>
+__device__ inline T* uniform_ptr(T* p) {
+    const uint64_t u = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+__device__ inline int64_t uniform_i64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+// A generic pointer known to address LDS: the result is generic again, but
+// derived from an LDS pointer, so accesses through it compile to LDS
+// instructions.
+template <typename T>
+__device__ inline T* as_lds(T* p) {
+    return (T*)(__attribute__((address_space(3))) T*)p;
+}
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -97,18 +152,18 @@ __device__ inline void load_idx(const LinArgs& A, int64_t cell, CellIdx<FORM, D,
     constexpr int NF = nfield(D, FD);
     const int32_t* cv = A.c2v + cell * (D + 1);
 #pragma unroll
-    for (int v = 0; v <= D; ++v) ix.v[v] = __builtin_nontemporal_load(cv + v);
+    for (int v = 0; v <= D; ++v) ix.v[v] = gload_nt(cv + v);
     if constexpr (FD > 0) {
         if (A.f0.map) {
             const int32_t* m = A.f0.map + cell * NF;
 #pragma unroll
-            for (int r = 0; r < NF; ++r) ix.f0[r] = __builtin_nontemporal_load(m + r);
+            for (int r = 0; r < NF; ++r) ix.f0[r] = gload_nt(m + r);
         }
         if constexpr (FORM == F_ELAST) {
             if (A.f1.map) {
                 const int32_t* m = A.f1.map + cell * NF;
 #pragma unroll
-                for (int r = 0; r < NF; ++r) ix.f1[r] = __builtin_nontemporal_load(m + r);
+                for (int r = 0; r < NF; ++r) ix.f1[r] = gload_nt(m + r);
             }
         }
     }
@@ -120,7 +175,7 @@ __device__ inline void load_field_vals(const FieldArg& f, int64_t cell, const in
     for (int r = 0; r < NL; ++r) {
         const int64_t base = f.map ? (int64_t)idx[r] * NCOMP : (cell * NL + r) * NCOMP;
 #pragma unroll
-        for (int c = 0; c < NCOMP; ++c) v[r * NCOMP + c] = f.values[base + c];
+        for (int c = 0; c < NCOMP; ++c) v[r * NCOMP + c] = gload(f.values + base + c);
     }
 }
 
@@ -131,7 +186,7 @@ __device__ inline void load_raw(const LinArgs& A, int64_t cell, const CellIdx<FO
 #pragma unroll
     for (int v = 0; v <= D; ++v)
 #pragma unroll
-        for (int i = 0; i < D; ++i) rw.x[v][i] = A.coords[(int64_t)ix.v[v] * D + i];
+        for (int i = 0; i < D; ++i) rw.x[v][i] = gload(A.coords + (int64_t)ix.v[v] * D + i);
     if constexpr (FD > 0) {
         load_field_vals<NF, CellRaw<FORM, D, FD>::WC>(A.f0, cell, ix.f0, rw.f0);
         if constexpr (FORM == F_ELAST) load_field_vals<NF, 1>(A.f1, cell, ix.f1, rw.f1);

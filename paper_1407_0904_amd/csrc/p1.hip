@@ -1,31 +1,22 @@
-// Degree-1 mass and Helmholtz: one thread per cell, FMA arithmetic.
-//
-// At p = 1 the element tensor is 3 x 3 (triangle) or 4 x 4 (tetrahedron) and
-// the collapsed contraction A[a][b] = sum_k G[k] R[k][a][b] (section 2, Fig. 1;
-// the quadrature sum folded into R as in linear.hpp) is a few hundred flops per
-// cell: far too small to fill an MFMA tile, and the cell's bytes dominate. So
-// each lane gathers its cell, forms J, |det J|, K = J^-1 and the G row in FP64
-// registers, and contracts it against R, whose entries every lane reads at the
-// same address (scalar loads into SGPR operands). The upper triangle a <= b is
-// formed and mirrored (the symmetric iteration space of the paper's j, k
-// loops). A wave's 64 tensors are staged in LDS (rows padded to an odd number
-// of elements, so that lanes writing their own rows hit distinct banks) and
-// leave as stores whose 64 lanes cover consecutive elements of the wave's
-// contiguous output range.
+// Degree-1 mass and Helmholtz: one thread per cell, FMA arithmetic (the
+// per-cell arithmetic is in p1.hpp). Each lane gathers its cell, forms J,
+// |det J|, K = J^-1 and the G row in FP64 registers and writes its tensor to
+// an LDS row; the wave's 64 tensors then leave as stores whose 64 lanes cover
+// consecutive elements of the wave's contiguous output range.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
 
 #include "library.h"
-#include "linear.hpp"
+#include "p1.hpp"
 
 namespace coffee {
 namespace dev {
 
 template <int FORM, int D, int FD, typename OT>
 __global__ __launch_bounds__(256) void k_p1(LinArgs A, const double* __restrict__ R) {
-    constexpr int NS = D + 1, NN = NS * NS, KR = kref(FORM, D, FD);
-    constexpr int SR = NN | 1;  // padded LDS row
+    constexpr int NN = (D + 1) * (D + 1), KR = kref(FORM, D, FD);
+    constexpr int SR = p1_row<D>();
     __shared__ OT stage[4][64 * SR];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     OT* st = stage[wave];
@@ -38,16 +29,7 @@ __global__ __launch_bounds__(256) void k_p1(LinArgs A, const double* __restrict_
     load_cell<FORM, D, FD>(A, cell, cd);
     double G[KR];
     build_G<FORM, D, FD, 0, 0>(cd, A, G);
-#pragma unroll
-    for (int a = 0; a < NS; ++a)
-#pragma unroll
-        for (int b = a; b < NS; ++b) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < KR; ++k) s += G[k] * R[k * NN + a * NS + b];
-            st[lane * SR + a * NS + b] = (OT)s;
-            st[lane * SR + b * NS + a] = (OT)s;
-        }
+    p1_tensor<FORM, D, FD, OT>(G, R, st + lane * SR);
     wave_sync();
     const int n = A.ncells - base < 64 ? (int)(A.ncells - base) : 64;
     OT* dst = out + base * NN;

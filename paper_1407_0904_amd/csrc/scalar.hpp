@@ -82,7 +82,7 @@ __device__ inline void scalar_contract(const ScalarWave<FORM, D, P, FD, PREC>& W
             if (t0 + t < C::NT) {
                 typename C::frag_t bf;
                 if constexpr (C::RREG) bf = W.rreg[t0 + t < C::NT ? t0 + t : 0][s];
-                else bf = W.rf[((t0 + t) * C::KS + s) * 64 + W.lane];
+                else bf = gload(W.rf + ((t0 + t) * C::KS + s) * 64 + W.lane);
                 acc[t] = mfma<PREC>(a, bf, acc[t]);
             }
         }
@@ -143,19 +143,19 @@ __device__ inline void scalar_tile(const LinArgs& A, ScalarWave<FORM, D, P, FD, 
 #pragma unroll
                     for (int i = 0; i < PL; ++i)
                         if (i * 64 + lane < NV) {
-                            __builtin_nontemporal_store(tmp[i], &d4p[i * 64 + lane]);
+                            gstore_nt(&d4p[i * 64 + lane], tmp[i]);
                         }
                     if constexpr (NV * PER16 != 8 * NN) {
                         constexpr int REM = 8 * NN - NV * PER16;  // < PER16 elements
-                        if (lane < REM) dst[NV * PER16 + lane] = W.stage[NV * PER16 + lane];
+                        if (lane < REM) gstore(&dst[NV * PER16 + lane], W.stage[NV * PER16 + lane]);
                     }
                 } else {
                     const int64_t nc = A.ncells - c0 < 8 ? A.ncells - c0 : 8;
                     if (nc > 0) {
                         const int nelem = (int)nc * NN;
                         const int nvec = nelem / PER16;
-                        for (int i = lane; i < nvec; i += 64) d4p[i] = s4[i];
-                        for (int i = nvec * PER16 + lane; i < nelem; i += 64) dst[i] = W.stage[i];
+                        for (int i = lane; i < nvec; i += 64) gstore(&d4p[i], s4[i]);
+                        for (int i = nvec * PER16 + lane; i < nelem; i += 64) gstore(&dst[i], W.stage[i]);
                     }
                 }
             }
@@ -173,8 +173,8 @@ __device__ inline void scalar_tile(const LinArgs& A, ScalarWave<FORM, D, P, FD, 
                     if (FULL || c < A.ncells) {
                         out_t* base = W.out + c * NN;
                         const out_t x = (out_t)acc[t][v];
-                        base[a * NS + bb] = x;
-                        base[bb * NS + a] = x;
+                        gstore(&base[a * NS + bb], x);
+                        gstore(&base[bb * NS + a], x);
                     }
                 }
             }
@@ -227,7 +227,7 @@ void k_scalar(LinArgs A) {
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int s = 0; s < KS; ++s) W.rreg[t][s] = W.rf[(t * KS + s) * 64 + lane];
+            for (int s = 0; s < KS; ++s) W.rreg[t][s] = gload(W.rf + (t * KS + s) * 64 + lane);
     }
 
     // Persistent loop over 256-cell chunks, XCD-contiguous ranges of chunks per
