@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "library.h"
@@ -452,7 +453,7 @@ __device__ __attribute__((noinline)) void batch_task(const BatchArgs* Ap, const 
 // of the bin's contiguous range (packed layout) or of each entry's own range
 // (caller's layout, offsets in LDS). The gathers of the next groups are issued
 // before the current group's stores, as in the symmetric tiles.
-template <int FORM, int D, int PREC, int VARIANT>
+template <int FORM, int D, int PREC, int VARIANT, int MAPF>
 __device__ __attribute__((noinline)) void batch_task_p1(const BatchArgs* Ap, const BinDesc* bdp, int bin, int64_t first,
                                                         int n, int lane, unsigned wave_off) {
     using out_t = typename PrecT<PREC>::otype;
@@ -484,67 +485,110 @@ __device__ __attribute__((noinline)) void batch_task_p1(const BatchArgs* Ap, con
         const int64_t p0 = at(0);
         const int c0 = gload(V.bcell + p0);
         o0 = off(p0);
-        load_idx<FORM, D, FD>(L, c0, ix);
-        load_raw<FORM, D, FD>(L, c0, ix, raw);
+        load_idx<FORM, D, FD, MAPF>(L, c0, ix);
+        load_raw<FORM, D, FD, MAPF>(L, c0, ix, raw);
         const int64_t p1 = at(1);
         c1 = gload(V.bcell + p1);
         o1 = off(p1);
-        load_idx<FORM, D, FD>(L, c1, ix);
+        load_idx<FORM, D, FD, MAPF>(L, c1, ix);
         const int64_t p2 = at(2);
         c2 = gload(V.bcell + p2);
         o2 = off(p2);
     }
-    for (int g = 0; g < ng; ++g) {
-        double G[KR];
-        {
-            CellData<FORM, D, FD> cd;
-            cell_from_raw<FORM, D, FD>(raw, cd);
-            build_G<FORM, D, FD, 0, 0>(cd, L, G);
-        }
-        p1_tensor<FORM, D, FD, out_t>(G, R, stage + lane * SR);
-        if constexpr (VARIANT != 2) soffs[lane] = o0;
-        load_raw<FORM, D, FD>(L, c1, ix, raw);  // group g + 1
-        load_idx<FORM, D, FD>(L, c2, ix);       // group g + 2
+    // Complete the prologue's loads before the loop, so that the loop is
+    // entered with nothing outstanding and its waits count only its own loads
+    // and stores.
+#pragma unroll
+    for (int v = 0; v <= D; ++v)
+#pragma unroll
+        for (int i = 0; i < D; ++i) asm volatile("" ::"v"(raw.x[v][i]));
+#pragma unroll
+    for (int r = 0; r < CellRaw<FORM, D, FD>::NF; ++r) asm volatile("" ::"v"(raw.f0[r]));
+#pragma unroll
+    for (int v = 0; v <= D; ++v) asm volatile("" ::"v"(ix.v[v]));
+#pragma unroll
+    for (int r = 0; r < CellIdx<FORM, D, FD>::NF; ++r) asm volatile("" ::"v"(ix.f0[r]));
+    asm volatile("" ::"v"(c1), "v"(c2), "v"(o0), "v"(o1), "v"(o2));
+    // One group: the next groups' gathers, then G and the tensors of the
+    // current group into LDS and this group's stores. FULL groups store a
+    // compile-time number of elements with no per-element condition, so the
+    // wait for the prefetched gathers does not have to drain the stores.
+    auto step = [&](int g, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        CellData<FORM, D, FD> cd;
+        cell_from_raw<FORM, D, FD>(raw, cd);          // group g
+        load_raw<FORM, D, FD, MAPF>(L, c1, ix, raw);  // group g + 1
+        load_idx<FORM, D, FD, MAPF>(L, c2, ix);       // group g + 2
         const int64_t p3 = at(g + 3);
         const int c3 = gload(V.bcell + p3);
         const int64_t o3 = off(p3);
+        // the gathers are issued before this group's arithmetic and stores,
+        // and nothing of the next group moves above them
+        __builtin_amdgcn_sched_barrier(0);
+        double G[KR];
+        build_G<FORM, D, FD, 0, 0>(cd, L, G);
+        p1_tensor<FORM, D, FD, out_t>(G, R, stage + lane * SR);
+        if constexpr (VARIANT != 2) soffs[lane] = o0;
         wave_sync();
-        const int m = n - 64 * g < 64 ? n - 64 * g : 64;
+        const int m = FULL ? 64 : n - 64 * g;
         out_t* dst = out + (int64_t)64 * g * NN;
+        out_t v[NN];
+        int64_t dd[NN];
 #pragma unroll
-        for (int i0 = 0; i0 < 64 * NN; i0 += 64) {
-            const int i = i0 + lane;
+        for (int k = 0; k < NN; ++k) {
+            const int i = k * 64 + lane;
             const int c = i / NN, e = i - (i / NN) * NN;
-            if (c < m) {
-                if constexpr (VARIANT == 2) gstore(&dst[i], stage[c * SR + e]);
-                else gstore(&out[soffs[c] + e], stage[c * SR + e]);
+            v[k] = stage[c * SR + e];
+            dd[k] = VARIANT == 2 ? (int64_t)i : soffs[c] + e;
+        }
+#pragma unroll
+        for (int k = 0; k < NN; ++k) {
+            if (FULL || (k * 64 + lane) / NN < m) {
+                if constexpr (VARIANT == 2) gstore(&dst[dd[k]], v[k]);
+                else gstore(&out[dd[k]], v[k]);
             }
         }
         wave_sync();
+        __builtin_amdgcn_sched_barrier(0);
         o0 = o1;
         o1 = o2;
         o2 = o3;
         c1 = c2;
         c2 = c3;
-    }
+    };
+    const int nfull = n >> 6;
+    for (int g = 0; g < nfull; ++g) step(g, std::true_type{});
+    if (nfull < ng) step(nfull, std::false_type{});
 }
 
 template <int PREC, int VARIANT>
-__device__ inline void batch_dispatch_v(const BatchArgs* A, const BinDesc* bd, int type, int bin, int64_t first,
-                                        int n, int lane, unsigned wave_off) {
+__device__ inline void batch_dispatch_v(const BatchArgs* A, const BinDesc* bd, int type, bool mapped, int bin,
+                                        int64_t first, int n, int lane, unsigned wave_off) {
     switch (type) {
-        case 0: batch_task_p1<F_MASS, 2, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 0:
+            if (mapped) batch_task_p1<F_MASS, 2, PREC, VARIANT, 1>(A, bd, bin, first, n, lane, wave_off);
+            else batch_task_p1<F_MASS, 2, PREC, VARIANT, 0>(A, bd, bin, first, n, lane, wave_off);
+            break;
         case 1: batch_task<F_MASS, 2, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
         case 2: batch_task<F_MASS, 2, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
         case 3: batch_task<F_MASS, 2, 4, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
-        case 4: batch_task_p1<F_MASS, 3, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 4:
+            if (mapped) batch_task_p1<F_MASS, 3, PREC, VARIANT, 1>(A, bd, bin, first, n, lane, wave_off);
+            else batch_task_p1<F_MASS, 3, PREC, VARIANT, 0>(A, bd, bin, first, n, lane, wave_off);
+            break;
         case 5: batch_task<F_MASS, 3, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
         case 6: batch_task<F_MASS, 3, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
-        case 7: batch_task_p1<F_HELM, 2, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 7:
+            if (mapped) batch_task_p1<F_HELM, 2, PREC, VARIANT, 1>(A, bd, bin, first, n, lane, wave_off);
+            else batch_task_p1<F_HELM, 2, PREC, VARIANT, 0>(A, bd, bin, first, n, lane, wave_off);
+            break;
         case 8: batch_task<F_HELM, 2, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
         case 9: batch_task<F_HELM, 2, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
         case 10: batch_task<F_HELM, 2, 4, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
-        case 11: batch_task_p1<F_HELM, 3, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
+        case 11:
+            if (mapped) batch_task_p1<F_HELM, 3, PREC, VARIANT, 1>(A, bd, bin, first, n, lane, wave_off);
+            else batch_task_p1<F_HELM, 3, PREC, VARIANT, 0>(A, bd, bin, first, n, lane, wave_off);
+            break;
         case 12: batch_task<F_HELM, 3, 2, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
         case 13: batch_task<F_HELM, 3, 3, 1, PREC, VARIANT>(A, bd, bin, first, n, lane, wave_off); break;
         default: break;
@@ -586,13 +630,14 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs* __restrict__ Ap,
             }
         const BinDesc* bd = &Ap->bins[b];
         const int tc = bd->task_cells, type = bd->type, variant = bd->variant;
+        const bool mapped = bd->f0.map != nullptr;
         const int64_t local = ((int64_t)t - tb) * tc;
         const int64_t cnt = (int64_t)A.counts[b];
         const int n = (int)(cnt - local < tc ? cnt - local : tc);
         const int64_t first = (int64_t)A.offs[b] + local;
-        if (variant == 2) batch_dispatch_v<PREC, 2>(Ap, bd, type, b, first, n, lane, wave_off);
-        else if (variant == 0) batch_dispatch_v<PREC, 0>(Ap, bd, type, b, first, n, lane, wave_off);
-        else batch_dispatch_v<PREC, 1>(Ap, bd, type, b, first, n, lane, wave_off);
+        if (variant == 2) batch_dispatch_v<PREC, 2>(Ap, bd, type, mapped, b, first, n, lane, wave_off);
+        else if (variant == 0) batch_dispatch_v<PREC, 0>(Ap, bd, type, mapped, b, first, n, lane, wave_off);
+        else batch_dispatch_v<PREC, 1>(Ap, bd, type, mapped, b, first, n, lane, wave_off);
     }
 }
 

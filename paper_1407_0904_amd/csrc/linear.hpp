@@ -147,14 +147,17 @@ struct CellRaw {
     double f1[(FORM == F_ELAST && FD > 0) ? NF : 1];
 };
 
-template <int FORM, int D, int FD>
+// MAPF: -1 tests at run time whether the first field has a dof map, 1 and 0
+// state that it has one or not (no branch: a branch around a load makes the
+// next wait for outstanding loads drain every earlier load and store).
+template <int FORM, int D, int FD, int MAPF = -1>
 __device__ inline void load_idx(const LinArgs& A, int64_t cell, CellIdx<FORM, D, FD>& ix) {
     constexpr int NF = nfield(D, FD);
     const int32_t* cv = A.c2v + cell * (D + 1);
 #pragma unroll
     for (int v = 0; v <= D; ++v) ix.v[v] = gload_nt(cv + v);
     if constexpr (FD > 0) {
-        if (A.f0.map) {
+        if (MAPF == 1 || (MAPF < 0 && A.f0.map)) {
             const int32_t* m = A.f0.map + cell * NF;
 #pragma unroll
             for (int r = 0; r < NF; ++r) ix.f0[r] = gload_nt(m + r);
@@ -169,17 +172,18 @@ __device__ inline void load_idx(const LinArgs& A, int64_t cell, CellIdx<FORM, D,
     }
 }
 
-template <int NL, int NCOMP>
+template <int NL, int NCOMP, int MAPF = -1>
 __device__ inline void load_field_vals(const FieldArg& f, int64_t cell, const int* idx, double* v) {
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
-        const int64_t base = f.map ? (int64_t)idx[r] * NCOMP : (cell * NL + r) * NCOMP;
+        const bool mapped = MAPF == 1 || (MAPF < 0 && f.map);
+        const int64_t base = mapped ? (int64_t)idx[r] * NCOMP : (cell * NL + r) * NCOMP;
 #pragma unroll
         for (int c = 0; c < NCOMP; ++c) v[r * NCOMP + c] = gload(f.values + base + c);
     }
 }
 
-template <int FORM, int D, int FD>
+template <int FORM, int D, int FD, int MAPF = -1>
 __device__ inline void load_raw(const LinArgs& A, int64_t cell, const CellIdx<FORM, D, FD>& ix,
                                 CellRaw<FORM, D, FD>& rw) {
     constexpr int NF = nfield(D, FD);
@@ -188,7 +192,7 @@ __device__ inline void load_raw(const LinArgs& A, int64_t cell, const CellIdx<FO
 #pragma unroll
         for (int i = 0; i < D; ++i) rw.x[v][i] = gload(A.coords + (int64_t)ix.v[v] * D + i);
     if constexpr (FD > 0) {
-        load_field_vals<NF, CellRaw<FORM, D, FD>::WC>(A.f0, cell, ix.f0, rw.f0);
+        load_field_vals<NF, CellRaw<FORM, D, FD>::WC, MAPF>(A.f0, cell, ix.f0, rw.f0);
         if constexpr (FORM == F_ELAST) load_field_vals<NF, 1>(A.f1, cell, ix.f1, rw.f1);
     }
 }

@@ -78,7 +78,7 @@ def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4
     return entries
 
 
-def tune_batch(mb, precision: str = "fp32", variants=(0, 1), task_cells=(128, 256, 512, 1024), log=print):
+def tune_batch(mb, precision: str = "fp32", variants=(0, 1), task_cells=(64, 128, 256, 512, 1024), log=print):
     """Best (variant, task_cells) per bin of a mixed batch, timed one bin at a time."""
     import torch
     from . import coffee
@@ -117,7 +117,7 @@ def tune_batch(mb, precision: str = "fp32", variants=(0, 1), task_cells=(128, 25
     return entries
 
 
-def tune_batch_packed(mb, precision: str = "fp32", task_cells=(128, 256, 512, 1024), log=print):
+def tune_batch_packed(mb, precision: str = "fp32", task_cells=(64, 128, 256, 512, 1024), log=print):
     """Best cells per task per bin of a mixed batch in the packed layout, timed one bin at a time."""
     import torch
     from . import coffee
