@@ -15,9 +15,11 @@
 // dphi_b/dX_b with H = w |det J| K C K^T, accumulated as two rank-structured
 // updates per point and reference direction.
 //
-// Work layout: energy and residual one thread per cell; Jacobian one thread per
-// (cell, block c <= c') holding that block's n x n accumulators, the mirrored
-// block written from the same values (the Jacobian is symmetric). Reference
+// Work layout: energy and residual one thread per cell. Jacobian: a wave takes
+// a few consecutive cells; F at each (cell, point) is formed once into LDS,
+// then each lane accumulates a slice of rows of one block c <= c' (the mirrored
+// block comes from the same values: the Jacobian is symmetric), and each cell's
+// tensor is staged in LDS and written as contiguous 16-byte stores. Reference
 // gradients and weights are staged in LDS and read at wave-uniform addresses.
 #include <hip/hip_runtime.h>
 
@@ -55,10 +57,10 @@ struct SvkPoint {
     double F[D][D], S[D][D];
 };
 
-// F and S at point q from the reference displacement gradient.
+// F = I + U K at point q from the reference displacement gradient.
 template <int D, int NS>
-__device__ inline void svk_point(const double (&uv)[NS * D], const double (&K)[D][D], const double* dphi_q, int nq,
-                                 double mu, double lm, SvkPoint<D>& pt, double* psi, double (&Pout)[D][D]) {
+__device__ inline void svk_F(const double (&uv)[NS * D], const double (&K)[D][D], const double* dphi_q, int nq,
+                             double (&F)[D][D]) {
     double U[D][D];  // U[i][a] = sum_r u_{r,i} dphi_r/dX_a
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -76,8 +78,36 @@ __device__ inline void svk_point(const double (&uv)[NS * D], const double (&K)[D
             double g = 0.0;
 #pragma unroll
             for (int a = 0; a < D; ++a) g += U[i][a] * K[a][j];
-            pt.F[i][j] = (i == j ? 1.0 : 0.0) + g;
+            F[i][j] = (i == j ? 1.0 : 0.0) + g;
         }
+}
+
+// S = lambda tr(E) I + 2 mu E with E = (F^T F - I) / 2.
+template <int D>
+__device__ inline void svk_S(const double (&F)[D][D], double mu, double lm, double (&S)[D][D]) {
+    double E[D][D], trE = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) t += F[k][i] * F[k][j];
+            E[i][j] = 0.5 * (t - (i == j ? 1.0 : 0.0));
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) trE += E[i][i];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) S[i][j] = (i == j ? lm * trE : 0.0) + 2.0 * mu * E[i][j];
+}
+
+// F and S at point q from the reference displacement gradient.
+template <int D, int NS>
+__device__ inline void svk_point(const double (&uv)[NS * D], const double (&K)[D][D], const double* dphi_q, int nq,
+                                 double mu, double lm, SvkPoint<D>& pt, double* psi, double (&Pout)[D][D]) {
+    svk_F<D, NS>(uv, K, dphi_q, nq, pt.F);
     double E[D][D], trE = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -135,6 +165,8 @@ __device__ inline void svk_load(const SvkArgs& A, int64_t cell, Geom<D>& g, doub
         for (int i = 0; i < D; ++i) uv[r * D + i] = A.u.values[base + i];
     }
 }
+
+typedef unsigned int svk_u32x4 __attribute__((ext_vector_type(4)));
 
 template <int D, int P>
 constexpr int svk_tab_elems(int nq) { return nq + D * nq * nsc(D, P); }
@@ -320,71 +352,111 @@ __global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
     }
 }
 
-// Jacobian: one thread per (cell, block c1 <= c2).
-template <int D, int P, int NQ, typename AT>
-__global__ __launch_bounds__(256) void k_svk_jacobian(SvkArgs A) {
+// Jacobian, shared-point layout: CPW cells per wave, lane (cell, block
+// c1 <= c2, row slice h) accumulating rows h*NA .. h*NA + NA - 1 of that block.
+// F and S at every (cell, point) are formed once, by the cell's lanes in turn,
+// into LDS. Each lane forms its block's H = w K C K^T from the tangent above
+// and accumulates its rows as A[a][b] += sum_be (sum_al dphi_al,a H[al][be])
+// dphi_be,b.
+template <int D, int P, int NQ, typename AT, int AH>
+__global__ __launch_bounds__(256, 2) void k_svk_jac(SvkArgs A) {
     constexpr int NS = nsc(D, P);
     constexpr int N = D * NS;
     constexpr int NB = D * (D + 1) / 2;
-    constexpr int CPW = 64 / NB;  // cells per wave
+    constexpr int LPC = NB * AH;  // lanes per cell
+    constexpr int CPW = 64 / LPC;  // cells per wave
+    constexpr int NA = (NS + AH - 1) / AH;
     constexpr int TE = NQ + D * NQ * NS;
+    // per wave: F and S (upper) at the group's points, later one cell's
+    // staged tensor
+    constexpr int PEQ = D * D + NB;
+    constexpr int FE = CPW * NQ * PEQ;
+    constexpr int SE = (N * N * (int)sizeof(AT) + 7) / 8;
     __shared__ double tab[TE];
+    constexpr int WE = ((FE > SE ? FE : SE) + 1) / 2 * 2;  // 16-byte multiple
+    __shared__ __attribute__((aligned(16))) double fbuf[4][WE];
     for (int i = threadIdx.x; i < TE; i += blockDim.x) tab[i] = A.tab[i];
     __syncthreads();
     const double* W = tab;
     const double* dphi = tab + NQ;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int blk = lane % NB, cl = lane / NB;
+    const int k = lane % LPC, cl = lane / LPC;
+    const int blk = k % NB, h = k / NB;
     int c1 = 0, c2 = 0;
     {
         int t = blk;
         while (t >= D - c1) { t -= D - c1; ++c1; }
         c2 = c1 + t;
     }
+    const int a0 = h * NA;
+    const double diag = c1 == c2 ? 1.0 : 0.0;
+    double* Fw = fbuf[wave];
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t w0 = (int64_t)blockIdx.x * 4 + wave; w0 * CPW < A.ncells; w0 += nwaves) {
         const int64_t cell = w0 * CPW + cl;
-        if (cl >= CPW || cell >= A.ncells) continue;
+        const bool active = cl < CPW && cell < A.ncells;
+        // lanes without a cell work on the group's last one and store nothing
+        const int64_t lcell = active ? cell : (w0 * CPW + CPW - 1 < A.ncells ? w0 * CPW + CPW - 1 : A.ncells - 1);
         Geom<D> g;
         double uv[NS * D];
         int vid[D + 1], uid[NS];
-        svk_load<D, NS>(A, cell, g, uv, vid, uid);
-        AT acc[NS][NS];
+        svk_load<D, NS>(A, lcell, g, uv, vid, uid);
+        double* Fc = Fw + (cl < CPW ? cl : CPW - 1) * NQ * PEQ;
+        // F at the cell's points, LPC points at a time
+#pragma unroll 1
+        for (int q = k; q < NQ; q += LPC) {
+            if (!active) break;
+            double F[D][D], S[D][D];
+            svk_F<D, NS>(uv, g.K, dphi + q * NS, NQ, F);
+            svk_S<D>(F, A.mu, A.lambda, S);
+            double* pq = Fc + q * PEQ;
 #pragma unroll
-        for (int a = 0; a < NS; ++a)
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) pq[i * D + j] = F[i][j];
+            int t = 0;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = i; j < D; ++j, ++t) pq[D * D + t] = S[i][j];
+        }
+        wave_sync();
+        AT acc[NA][NS];
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
 #pragma unroll
             for (int b = 0; b < NS; ++b) acc[a][b] = (AT)0;
 #pragma unroll 1
         for (int q = 0; q < NQ; ++q) {
-            SvkPoint<D> pt;
-            double Pm[D][D];
-            svk_point<D, NS>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, nullptr, Pm);
-            // rows c1 and c2 of F (selected without lane-dependent register indexing)
+            const double* Fq = Fc + q * PEQ;
             double F1[D], F2[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                F1[k] = pt.F[0][k];
-                F2[k] = pt.F[0][k];
+            for (int j = 0; j < D; ++j) {
+                F1[j] = Fq[c1 * D + j];
+                F2[j] = Fq[c2 * D + j];
             }
+            // S enters the diagonal blocks only
+            double S[D][D];
+            {
+                int t = 0;
 #pragma unroll
-            for (int i = 1; i < D; ++i)
+                for (int i = 0; i < D; ++i)
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    F1[k] = (c1 == i) ? pt.F[i][k] : F1[k];
-                    F2[k] = (c2 == i) ? pt.F[i][k] : F2[k];
-                }
-            // tangent block C[j][l] = C_(c1 j c2 l)
+                    for (int j = i; j < D; ++j, ++t) {
+                        S[i][j] = diag * Fq[D * D + t];
+                        S[j][i] = S[i][j];
+                    }
+            }
             double FF = 0.0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) FF += F1[k] * F2[k];
+            for (int j = 0; j < D; ++j) FF += F1[j] * F2[j];
             double C[D][D];
 #pragma unroll
             for (int j = 0; j < D; ++j)
 #pragma unroll
                 for (int l = 0; l < D; ++l)
-                    C[j][l] = (c1 == c2 ? pt.S[l][j] : 0.0) + A.lambda * F1[j] * F2[l] + A.mu * F1[l] * F2[j] +
+                    C[j][l] = S[l][j] + A.lambda * F1[j] * F2[l] + A.mu * F1[l] * F2[j] +
                               (j == l ? A.mu * FF : 0.0);
-            // H = w K C K^T (the |det J| factor is applied at the end)
             double KC[D][D], H[D][D];
 #pragma unroll
             for (int a = 0; a < D; ++a)
@@ -404,35 +476,70 @@ __global__ __launch_bounds__(256) void k_svk_jacobian(SvkArgs A) {
                     for (int l = 0; l < D; ++l) s += KC[a][l] * g.K[b][l];
                     H[a][b] = W[q] * s;
                 }
-            // acc[a][b] += sum_al dphi_al,a (sum_be H[al][be] dphi_be,b)
+            // this lane's rows: wv[i][be] = sum_al dphi_al,a H[al][be], then
+            // A[a][b] += sum_be wv[i][be] dphi_be,b
+            AT wv[NA][D];
 #pragma unroll
-            for (int al = 0; al < D; ++al) {
-                AT v[NS];
+            for (int i = 0; i < NA; ++i) {
+                const int a = a0 + i < NS ? a0 + i : NS - 1;
 #pragma unroll
-                for (int b = 0; b < NS; ++b) {
+                for (int be = 0; be < D; ++be) {
                     double s = 0.0;
 #pragma unroll
-                    for (int be = 0; be < D; ++be) s += H[al][be] * dphi[(size_t)be * NQ * NS + q * NS + b];
-                    v[b] = (AT)s;
-                }
-#pragma unroll
-                for (int a = 0; a < NS; ++a) {
-                    const AT da = (AT)dphi[(size_t)al * NQ * NS + q * NS + a];
-#pragma unroll
-                    for (int b = 0; b < NS; ++b) acc[a][b] += da * v[b];
+                    for (int al = 0; al < D; ++al) s += dphi[(size_t)al * NQ * NS + q * NS + a] * H[al][be];
+                    wv[i][be] = (AT)s;
                 }
             }
+#pragma unroll
+            for (int be = 0; be < D; ++be)
+#pragma unroll
+                for (int b = 0; b < NS; ++b) {
+                    const AT db = (AT)dphi[(size_t)be * NQ * NS + q * NS + b];
+#pragma unroll
+                    for (int i = 0; i < NA; ++i) acc[i][b] += wv[i][be] * db;
+                }
         }
+        wave_sync();  // the next cell's F overwrites this one's
         const AT ad = (AT)g.adet;
-        AT* o = reinterpret_cast<AT*>(A.out) + cell * (int64_t)N * N;
+        // the wave's cells are consecutive: stage each cell's tensor in LDS
+        // (over the point data, no longer needed) and write it as contiguous
+        // 16-byte stores
+        AT* stg = reinterpret_cast<AT*>(Fw);
+        AT* out = reinterpret_cast<AT*>(A.out);
+        wave_sync();
+#pragma unroll 1
+        for (int r = 0; r < CPW; ++r) {
+            const int64_t rc = w0 * CPW + r;
+            if (rc >= A.ncells) break;  // wave-uniform
+            if (active && cl == r) {
 #pragma unroll
-        for (int a = 0; a < NS; ++a)
+                for (int i = 0; i < NA; ++i) {
+                    const int a = a0 + i;
+                    if (a >= NS) continue;
 #pragma unroll
-            for (int b = 0; b < NS; ++b) {
-                const AT x = ad * acc[a][b];
-                o[(c1 * NS + a) * N + c2 * NS + b] = x;
-                if (c1 != c2) o[(c2 * NS + b) * N + c1 * NS + a] = x;
+                    for (int b = 0; b < NS; ++b) {
+                        const AT x = ad * acc[i][b];
+                        stg[(c1 * NS + a) * N + c2 * NS + b] = x;
+                        if (c1 != c2) stg[(c2 * NS + b) * N + c1 * NS + a] = x;
+                    }
+                }
             }
+            wave_sync();
+            AT* o = out + rc * (int64_t)N * N;
+            if constexpr ((N * N * sizeof(AT)) % 16 == 0) {
+                constexpr int NV = (int)(N * N * sizeof(AT) / 16);
+                const svk_u32x4* s4 = reinterpret_cast<const svk_u32x4*>(stg);
+                svk_u32x4* o4 = reinterpret_cast<svk_u32x4*>(o);
+#pragma unroll
+                for (int e0 = 0; e0 < NV; e0 += 64)
+                    if (e0 + lane < NV) __builtin_nontemporal_store(s4[e0 + lane], &o4[e0 + lane]);
+            } else {
+#pragma unroll
+                for (int e0 = 0; e0 < N * N; e0 += 64)
+                    if (e0 + lane < N * N) o[e0 + lane] = stg[e0 + lane];
+            }
+            wave_sync();
+        }
     }
 }
 
@@ -490,6 +597,8 @@ void free_svk_tables() {
 
 namespace {
 
+constexpr int svk_jac_slices(int, int p) { return p == 2 ? 2 : 1; }
+
 // compiled set: triangles and tetrahedra, P1 (q = 2, evaluated at one point
 // with the summed weight) and P2 (q = 4)
 template <int D, int P, int NQ>
@@ -509,12 +618,14 @@ hipError_t launch_svk(int form, int precision, const dev::SvkArgs& a, hipStream_
         if (f64) hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 1, double>), dim3(grid), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 1, float>), dim3(grid), dim3(256), 0, s, a);
     } else {
-        constexpr int NB = D * (D + 1) / 2;
-        constexpr int CPW = 64 / NB;
+        // row slices per block: enough to keep the accumulators of a P2
+        // tetrahedron block well under the register file of 2 waves per SIMD
+        constexpr int AH = svk_jac_slices(D, P);
+        constexpr int CPW = 64 / (D * (D + 1) / 2 * AH);
         const int64_t waves = (a.ncells + CPW - 1) / CPW;
         const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, (int64_t)ncu * 16));
-        if (f64) hipLaunchKernelGGL((dev::k_svk_jacobian<D, P, NQ, double>), dim3(g2), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((dev::k_svk_jacobian<D, P, NQ, float>), dim3(g2), dim3(256), 0, s, a);
+        if (f64) hipLaunchKernelGGL((dev::k_svk_jac<D, P, NQ, double, AH>), dim3(g2), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((dev::k_svk_jac<D, P, NQ, float, AH>), dim3(g2), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
