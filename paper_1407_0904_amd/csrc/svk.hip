@@ -371,9 +371,13 @@ __global__ __launch_bounds__(256, 2) void k_svk_jac(SvkArgs A) {
     // staged tensor
     constexpr int PEQ = D * D + NB;
     constexpr int FE = CPW * NQ * PEQ;
-    constexpr int SE = (N * N * (int)sizeof(AT) + 7) / 8;
+    constexpr int SE = (N * N * (int)sizeof(AT) + 7) / 8;  // one staged cell, in doubles
+    // cells staged per round: as many as the point data's area holds, or as
+    // fit in 6 KiB
+    constexpr int CR0 = FE / SE > 6144 / (SE * 8) ? FE / SE : 6144 / (SE * 8);
+    constexpr int CR = CR0 < 1 ? 1 : (CR0 > CPW ? CPW : CR0);
     __shared__ double tab[TE];
-    constexpr int WE = ((FE > SE ? FE : SE) + 1) / 2 * 2;  // 16-byte multiple
+    constexpr int WE = ((FE > CR * SE ? FE : CR * SE) + 1) / 2 * 2;  // 16-byte multiple
     __shared__ __attribute__((aligned(16))) double fbuf[4][WE];
     for (int i = threadIdx.x; i < TE; i += blockDim.x) tab[i] = A.tab[i];
     __syncthreads();
@@ -501,17 +505,22 @@ __global__ __launch_bounds__(256, 2) void k_svk_jac(SvkArgs A) {
         }
         wave_sync();  // the next cell's F overwrites this one's
         const AT ad = (AT)g.adet;
-        // the wave's cells are consecutive: stage each cell's tensor in LDS
-        // (over the point data, no longer needed) and write it as contiguous
-        // 16-byte stores
+        // the wave's cells are consecutive: stage CR cells' tensors at a time in
+        // LDS (over the point data, no longer needed) and write them as
+        // contiguous 16-byte stores
         AT* stg = reinterpret_cast<AT*>(Fw);
         AT* out = reinterpret_cast<AT*>(A.out);
         wave_sync();
 #pragma unroll 1
-        for (int r = 0; r < CPW; ++r) {
-            const int64_t rc = w0 * CPW + r;
+        for (int r0 = 0; r0 < CPW; r0 += CR) {
+            const int64_t rc = w0 * CPW + r0;
             if (rc >= A.ncells) break;  // wave-uniform
-            if (active && cl == r) {
+            // cells of this round: CR, fewer in the group's last round and at
+            // the end of the mesh
+            const int nc = CPW - r0 < CR ? CPW - r0 : CR;
+            const int nr = (int)(A.ncells - rc < nc ? A.ncells - rc : nc);
+            if (active && cl >= r0 && cl < r0 + CR) {
+                AT* sc = stg + (cl - r0) * N * N;
 #pragma unroll
                 for (int i = 0; i < NA; ++i) {
                     const int a = a0 + i;
@@ -519,8 +528,8 @@ __global__ __launch_bounds__(256, 2) void k_svk_jac(SvkArgs A) {
 #pragma unroll
                     for (int b = 0; b < NS; ++b) {
                         const AT x = ad * acc[i][b];
-                        stg[(c1 * NS + a) * N + c2 * NS + b] = x;
-                        if (c1 != c2) stg[(c2 * NS + b) * N + c1 * NS + a] = x;
+                        sc[(c1 * NS + a) * N + c2 * NS + b] = x;
+                        if (c1 != c2) sc[(c2 * NS + b) * N + c1 * NS + a] = x;
                     }
                 }
             }
@@ -528,15 +537,17 @@ __global__ __launch_bounds__(256, 2) void k_svk_jac(SvkArgs A) {
             AT* o = out + rc * (int64_t)N * N;
             if constexpr ((N * N * sizeof(AT)) % 16 == 0) {
                 constexpr int NV = (int)(N * N * sizeof(AT) / 16);
+                const int nv = nr * NV;
                 const svk_u32x4* s4 = reinterpret_cast<const svk_u32x4*>(stg);
                 svk_u32x4* o4 = reinterpret_cast<svk_u32x4*>(o);
 #pragma unroll
-                for (int e0 = 0; e0 < NV; e0 += 64)
-                    if (e0 + lane < NV) __builtin_nontemporal_store(s4[e0 + lane], &o4[e0 + lane]);
+                for (int e0 = 0; e0 < CR * NV; e0 += 64)
+                    if (e0 + lane < nv) __builtin_nontemporal_store(s4[e0 + lane], &o4[e0 + lane]);
             } else {
+                const int ne = nr * N * N;
 #pragma unroll
-                for (int e0 = 0; e0 < N * N; e0 += 64)
-                    if (e0 + lane < N * N) o[e0 + lane] = stg[e0 + lane];
+                for (int e0 = 0; e0 < CR * N * N; e0 += 64)
+                    if (e0 + lane < ne) o[e0 + lane] = stg[e0 + lane];
             }
             wave_sync();
         }

@@ -214,3 +214,26 @@ def test_packed_batch_full_size_sampled(cf):
         nn = A.shape[1]
         gidx = torch.as_tensor((exp_off[pick][:, None] + np.arange(nn)[None, :]).reshape(-1), device=got.device)
         np.testing.assert_array_equal(got[gidx].reshape(len(pick), nn).cpu().numpy(), A.cpu().numpy())
+
+
+@pytest.mark.parametrize("packed", [False, True])
+def test_batch_cell_major_field(cf, packed):
+    """A field given cell-major (no dof map) gives the same bits as the same
+    values behind a dof map, in every bin, in both layouts."""
+    import torch
+    mb = I.mixed_batch(n_tri=16, n_tet=4, tri_counts=(150, 100, 80, 50), tet_counts=(120, 80, 60), seed=11)
+    segs, (seg_of, cell_of, offs) = device_batch(cf, mb, variant=[b % 2 for b in range(14)], task_cells=128)
+    cm = []
+    for sg in segs:
+        v = sg.coeff.values[sg.coeff.cell_to_dof.long()].contiguous()  # [E, nloc, 1]
+        cm.append(cf.Segment(sg.form, sg.cell, sg.degree, sg.coords, sg.cell_to_vertex,
+                             cf.DeviceField(v, None, 1, 1), variant=sg.variant, task_cells=sg.task_cells))
+    if packed:
+        a, oa = cf.coffee_assemble_batch_packed(segs, seg_of, cell_of, mb.total_elems, precision="fp64")
+        b, ob = cf.coffee_assemble_batch_packed(cm, seg_of, cell_of, mb.total_elems, precision="fp64")
+        assert torch.equal(oa, ob)
+    else:
+        a = cf.coffee_assemble_batch(segs, seg_of, cell_of, offs, mb.total_elems, precision="fp64")
+        b = cf.coffee_assemble_batch(cm, seg_of, cell_of, offs, mb.total_elems, precision="fp64")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())

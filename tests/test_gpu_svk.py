@@ -94,3 +94,24 @@ def test_svk_full_size_sampled(cf, oracle):
             print(f"svk_p2_tet full {form} {prec}: {err:.3e}")
             assert err < TOL[prec]
             del out
+
+
+@pytest.mark.parametrize("d,p", [(3, 2), (3, 1), (2, 2)])
+def test_svk_jacobian_ragged_counts(cf, oracle, d, p):
+    """Cell counts that leave the last group of a wave partly empty (and a
+    single cell), with the displacement given through a dof map and cell-major."""
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    rng = np.random.default_rng(70 + 10 * d + p)
+    mesh = I.make_mesh(d, 9 if d == 2 else 4, 0.1, rng)
+    u = _disp(mesh, p, rng)
+    ucm = I.Field(np.ascontiguousarray(u.values[u.cell_to_dof]), None, u.degree, u.ncomp)
+    cst = [1.1, 0.9]
+    for count in (1, 4, 5, 6, 11, 37):
+        sub = I.Mesh(mesh.d, mesh.n, mesh.coords, np.ascontiguousarray(mesh.cells[:count]))
+        ref = oracle.assemble("svk_jacobian", mesh, p, fields=[u], constants=cst, cells=np.arange(count))
+        mapped = I.Field(u.values, np.ascontiguousarray(u.cell_to_dof[:count]), u.degree, u.ncomp)
+        cellmajor = I.Field(np.ascontiguousarray(ucm.values[:count]), None, u.degree, u.ncomp)
+        for f in (mapped, cellmajor):
+            got = assemble_gpu("svk_jacobian", sub, p, [f], constants=cst, precision="fp64").cpu().numpy()
+            err = cell_rel_err(got.reshape(count, -1), ref.reshape(count, -1))
+            assert err < TOL["fp64"], (count, f.cell_to_dof is None, err)
