@@ -206,7 +206,9 @@ __global__ __launch_bounds__(256) void k_adjoint_linear(AdjArgs A) {
 //     G = |det J| (mu_r (delta_c1c2 (K K^T)_ab + K[a][c2] K[b][c1]) + lambda_r K[a][c1] K[b][c2])
 // (the same arithmetic as reverse_G in linear.hpp, per entry instead of per
 // block). lam_e stays in registers, u_e rows are re-read per dof r (L1), R is
-// read from LDS with wave-uniform addresses. Per cell: NF D^2 NC (NS^2 +
+// read through the scalar path (its addresses are the same in every lane; from
+// LDS each wave-wide read of one value would cost as much LDS bandwidth as a
+// read of 64 different values). Per cell: NF D^2 NC (NS^2 +
 // NC NS) multiply-adds for the values (14k for P2 tetrahedra, against 32k for
 // the per-block contraction), and the dof r's coefficient bars are added to
 // the global gradients as soon as its loop ends.
@@ -221,9 +223,7 @@ template <int D, int P, int FD>
 __global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
     constexpr int NS = nsc(D, P), NN = NS * NS, NC = D, N = NC * NS;
     constexpr int NF = nfield(D, FD), KR = NF * D * D;
-    __shared__ double sR[KR * NN];
-    for (int i = threadIdx.x; i < KR * NN; i += blockDim.x) sR[i] = A.R[i];
-    __syncthreads();
+    (void)KR;
     for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.L.ncells;
          cell += (int64_t)gridDim.x * blockDim.x) {
         CellIdx<F_ELAST, D, FD> ix;
@@ -272,13 +272,13 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
                         Ka[i] = x;
                         Kb[i] = y;
                     }
-                    const double* Rk = sR + (r * D * D + ab) * NN;
+                    const double* Rk = A.R + (r * D * D + ab) * NN;
                     double V[NS];
 #pragma unroll
                     for (int a = 0; a < NS; ++a) {
                         double v = 0.0;
 #pragma unroll
-                        for (int b = 0; b < NS; ++b) v += Rk[a * NS + b] * u[b];
+                        for (int b = 0; b < NS; ++b) v += cload(Rk + a * NS + b) * u[b];
                         V[a] = v;
                     }
                     double kk = 0.0;  // (K K^T)_{alpha beta}
