@@ -498,7 +498,8 @@ __global__ __launch_bounds__(256, 2) void k_svk_jac(SvkArgs A) {
             for (int be = 0; be < D; ++be)
 #pragma unroll
                 for (int b = 0; b < NS; ++b) {
-                    const AT db = (AT)dphi[(size_t)be * NQ * NS + q * NS + b];
+                    // wave-uniform: through the scalar path, not an LDS broadcast
+                    const AT db = (AT)cload(A.tab + NQ + (size_t)be * NQ * NS + q * NS + b);
 #pragma unroll
                     for (int i = 0; i < NA; ++i) acc[i][b] += wv[i][be] * db;
                 }
