@@ -20,7 +20,8 @@
 // then each lane accumulates a slice of rows of one block c <= c' (the mirrored
 // block comes from the same values: the Jacobian is symmetric), and each cell's
 // tensor is staged in LDS and written as contiguous 16-byte stores. Reference
-// gradients and weights are staged in LDS and read at wave-uniform addresses.
+// gradients and weights are read at wave-uniform addresses through the scalar
+// path (staged in LDS where the Jacobian's lanes read different rows).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,8 +58,16 @@ struct SvkPoint {
     double F[D][D], S[D][D];
 };
 
+// Reference-table read: through the scalar path when the address is the same
+// in every lane (SC), else a plain (LDS) read.
+template <bool SC>
+__device__ inline double tread(const double* p) {
+    if constexpr (SC) return cload(p);
+    else return *p;
+}
+
 // F = I + U K at point q from the reference displacement gradient.
-template <int D, int NS>
+template <int D, int NS, bool SC = false>
 __device__ inline void svk_F(const double (&uv)[NS * D], const double (&K)[D][D], const double* dphi_q, int nq,
                              double (&F)[D][D]) {
     double U[D][D];  // U[i][a] = sum_r u_{r,i} dphi_r/dX_a
@@ -68,7 +77,7 @@ __device__ inline void svk_F(const double (&uv)[NS * D], const double (&K)[D][D]
         for (int a = 0; a < D; ++a) {
             double s = 0.0;
 #pragma unroll
-            for (int r = 0; r < NS; ++r) s += uv[r * D + i] * dphi_q[(size_t)a * nq * NS + r];
+            for (int r = 0; r < NS; ++r) s += uv[r * D + i] * tread<SC>(dphi_q + (size_t)a * nq * NS + r);
             U[i][a] = s;
         }
 #pragma unroll
@@ -104,10 +113,10 @@ __device__ inline void svk_S(const double (&F)[D][D], double mu, double lm, doub
 }
 
 // F and S at point q from the reference displacement gradient.
-template <int D, int NS>
+template <int D, int NS, bool SC = false>
 __device__ inline void svk_point(const double (&uv)[NS * D], const double (&K)[D][D], const double* dphi_q, int nq,
                                  double mu, double lm, SvkPoint<D>& pt, double* psi, double (&Pout)[D][D]) {
-    svk_F<D, NS>(uv, K, dphi_q, nq, pt.F);
+    svk_F<D, NS, SC>(uv, K, dphi_q, nq, pt.F);
     double E[D][D], trE = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -175,12 +184,9 @@ constexpr int svk_tab_elems(int nq) { return nq + D * nq * nsc(D, P); }
 template <int D, int P, int NQ, int MODE, typename OT>
 __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
     constexpr int NS = nsc(D, P);
-    constexpr int TE = NQ + D * NQ * NS;
-    __shared__ double tab[TE];
-    for (int i = threadIdx.x; i < TE; i += blockDim.x) tab[i] = A.tab[i];
-    __syncthreads();
-    const double* W = tab;
-    const double* dphi = tab + NQ;
+    // every table read below has the same address in all lanes: scalar path
+    const double* W = A.tab;
+    const double* dphi = A.tab + NQ;
     for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.ncells;
          cell += (int64_t)gridDim.x * blockDim.x) {
         Geom<D> g;
@@ -204,8 +210,8 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
         for (int q = 0; q < NQ; ++q) {
             SvkPoint<D> pt;
             double psi, Pm[D][D];
-            svk_point<D, NS>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, &psi, Pm);
-            const double wq = W[q];
+            svk_point<D, NS, true>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, &psi, Pm);
+            const double wq = cload(W + q);
             energy += wq * psi;
             if constexpr (MODE == 1) {
                 // b_(c,a) += w sum_al (P K^T)_c,al dphi_a/dX_al
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
                 for (int a = 0; a < NS; ++a) {
                     double dp[D];
 #pragma unroll
-                    for (int al = 0; al < D; ++al) dp[al] = dphi[(size_t)al * NQ * NS + q * NS + a];
+                    for (int al = 0; al < D; ++al) dp[al] = cload(dphi + (size_t)al * NQ * NS + q * NS + a);
 #pragma unroll
                     for (int c = 0; c < D; ++c) {
                         double t = 0.0;
@@ -242,7 +248,7 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
                     for (int al = 0; al < D; ++al) {
                         double s = 0.0;
 #pragma unroll
-                        for (int r = 0; r < NS; ++r) s += uv[r * D + i] * dphi[(size_t)al * NQ * NS + q * NS + r];
+                        for (int r = 0; r < NS; ++r) s += uv[r * D + i] * cload(dphi + (size_t)al * NQ * NS + q * NS + r);
                         U[i][al] = s;
                     }
 #pragma unroll
@@ -302,12 +308,9 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
 template <int D, int P, int NQ>
 __global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
     constexpr int NS = nsc(D, P);
-    constexpr int TE = NQ + D * NQ * NS;
-    __shared__ double tab[TE];
-    for (int i = threadIdx.x; i < TE; i += blockDim.x) tab[i] = A.tab[i];
-    __syncthreads();
-    const double* W = tab;
-    const double* dphi = tab + NQ;
+    // every table read below has the same address in all lanes: scalar path
+    const double* W = A.tab;
+    const double* dphi = A.tab + NQ;
     for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.ncells;
          cell += (int64_t)gridDim.x * blockDim.x) {
         Geom<D> g;
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
         for (int q = 0; q < NQ; ++q) {
             SvkPoint<D> pt;
             double Pm[D][D];
-            svk_point<D, NS>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, nullptr, Pm);
+            svk_point<D, NS, true>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, nullptr, Pm);
             double Q[D][D];
 #pragma unroll
             for (int c = 0; c < D; ++c)
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
                     double t = 0.0;
 #pragma unroll
                     for (int j = 0; j < D; ++j) t += Pm[c][j] * g.K[al][j];
-                    Q[c][al] = W[q] * t;
+                    Q[c][al] = cload(W + q) * t;
                 }
 #pragma unroll
             for (int a = 0; a < NS; ++a)
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
                 for (int c = 0; c < D; ++c) {
                     double t = 0.0;
 #pragma unroll
-                    for (int al = 0; al < D; ++al) t += Q[c][al] * dphi[(size_t)al * NQ * NS + q * NS + a];
+                    for (int al = 0; al < D; ++al) t += Q[c][al] * cload(dphi + (size_t)al * NQ * NS + q * NS + a);
                     res[c * NS + a] += t;
                 }
         }
