@@ -357,8 +357,10 @@ __global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
 
 // Jacobian, shared-point layout: CPW cells per wave, lane (cell, block
 // c1 <= c2, row slice h) accumulating rows h*NA .. h*NA + NA - 1 of that block.
-// F and S at every (cell, point) are formed once, by the cell's lanes in turn,
-// into LDS. Each lane forms its block's H = w K C K^T from the tangent above
+// At every (cell, point), F and S^ = K S K^T are formed once, by the cell's
+// lanes in turn, into LDS. Each lane forms its block's H = w K C K^T for the
+// tangent above, with k_c = K F_c (row c of F mapped by K), as
+//   H = w (delta_c1c2 S^ + lambda k_c1 k_c2^T + mu k_c2 k_c1^T + mu (F_c1 . F_c2) K K^T)
 // and accumulates its rows as A[a][b] += sum_be (sum_al dphi_al,a H[al][be])
 // dphi_be,b.
 template <int D, int P, int NQ, typename AT, int AH>
@@ -408,24 +410,50 @@ __global__ __launch_bounds__(256, 2) void k_svk_jac(SvkArgs A) {
         double uv[NS * D];
         int vid[D + 1], uid[NS];
         svk_load<D, NS>(A, lcell, g, uv, vid, uid);
+        double M[D][D];  // K K^T
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                double x = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) x += g.K[a][i] * g.K[b][i];
+                M[a][b] = x;
+            }
         double* Fc = Fw + (cl < CPW ? cl : CPW - 1) * NQ * PEQ;
         // F at the cell's points, LPC points at a time
 #pragma unroll 1
         for (int q = k; q < NQ; q += LPC) {
             if (!active) break;
-            double F[D][D], S[D][D];
+            double F[D][D], S[D][D], KS[D][D];
             svk_F<D, NS>(uv, g.K, dphi + q * NS, NQ, F);
             svk_S<D>(F, A.mu, A.lambda, S);
             double* pq = Fc + q * PEQ;
 #pragma unroll
-            for (int i = 0; i < D; ++i)
+            for (int c = 0; c < D; ++c)
 #pragma unroll
-                for (int j = 0; j < D; ++j) pq[i * D + j] = F[i][j];
+                for (int a = 0; a < D; ++a) pq[c * D + a] = F[c][a];
+            // S^ = K S K^T (upper)
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int l = 0; l < D; ++l) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) x += g.K[a][j] * S[j][l];
+                    KS[a][l] = x;
+                }
             int t = 0;
 #pragma unroll
-            for (int i = 0; i < D; ++i)
+            for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int j = i; j < D; ++j, ++t) pq[D * D + t] = S[i][j];
+                for (int b = a; b < D; ++b, ++t) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int l = 0; l < D; ++l) x += KS[a][l] * g.K[b][l];
+                    pq[D * D + t] = x;
+                }
+
         }
         wave_sync();
         AT acc[NA][NS];
@@ -436,53 +464,46 @@ __global__ __launch_bounds__(256, 2) void k_svk_jac(SvkArgs A) {
 #pragma unroll 1
         for (int q = 0; q < NQ; ++q) {
             const double* Fq = Fc + q * PEQ;
-            double F1[D], F2[D];
+            // rows c1, c2 of F; k_c = K F_c
+            double F1[D], F2[D], k1[D], k2[D], Sh[D][D];
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 F1[j] = Fq[c1 * D + j];
                 F2[j] = Fq[c2 * D + j];
             }
-            // S enters the diagonal blocks only
-            double S[D][D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double x = 0.0, y = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    x += g.K[a][j] * F1[j];
+                    y += g.K[a][j] * F2[j];
+                }
+                k1[a] = x;
+                k2[a] = y;
+            }
+            // S^ enters the diagonal blocks only
             {
                 int t = 0;
 #pragma unroll
-                for (int i = 0; i < D; ++i)
+                for (int a = 0; a < D; ++a)
 #pragma unroll
-                    for (int j = i; j < D; ++j, ++t) {
-                        S[i][j] = diag * Fq[D * D + t];
-                        S[j][i] = S[i][j];
+                    for (int b = a; b < D; ++b, ++t) {
+                        Sh[a][b] = diag * Fq[D * D + t];
+                        Sh[b][a] = Sh[a][b];
                     }
             }
             double FF = 0.0;
 #pragma unroll
             for (int j = 0; j < D; ++j) FF += F1[j] * F2[j];
-            double C[D][D];
-#pragma unroll
-            for (int j = 0; j < D; ++j)
-#pragma unroll
-                for (int l = 0; l < D; ++l)
-                    C[j][l] = S[l][j] + A.lambda * F1[j] * F2[l] + A.mu * F1[l] * F2[j] +
-                              (j == l ? A.mu * FF : 0.0);
-            double KC[D][D], H[D][D];
+            // H = w K C K^T = w (delta S^ + lambda k1 k2^T + mu k2 k1^T + mu FF K K^T)
+            double H[D][D];
+            const double wq = W[q];
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int l = 0; l < D; ++l) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) s += g.K[a][j] * C[j][l];
-                    KC[a][l] = s;
-                }
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-#pragma unroll
-                for (int b = 0; b < D; ++b) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int l = 0; l < D; ++l) s += KC[a][l] * g.K[b][l];
-                    H[a][b] = W[q] * s;
-                }
+                for (int b = 0; b < D; ++b)
+                    H[a][b] = wq * (Sh[a][b] + A.lambda * k1[a] * k2[b] + A.mu * k2[a] * k1[b] + A.mu * FF * M[a][b]);
             // this lane's rows: wv[i][be] = sum_al dphi_al,a H[al][be], then
             // A[a][b] += sum_be wv[i][be] dphi_be,b
             AT wv[NA][D];
