@@ -224,8 +224,21 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
     constexpr int NS = nsc(D, P), NN = NS * NS, NC = D, N = NC * NS;
     constexpr int NF = nfield(D, FD), KR = NF * D * D;
     (void)KR;
-    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.L.ncells;
-         cell += (int64_t)gridDim.x * blockDim.x) {
+    // per-wave combining of the gradient scatter-adds (vertex coordinates,
+    // then the two fields' dofs)
+    constexpr int TS = 256;
+    __shared__ unsigned long long ckx[4][TS], ckf[4][2][TS];
+    __shared__ double cvx[4][TS * D], cvf[4][2][TS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wave-uniform loop: every lane takes part in the tables' clear and flush
+    for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) - lane; base < A.L.ncells;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const bool valid = base + lane < A.L.ncells;
+        const int64_t cell = valid ? base + lane : A.L.ncells - 1;
+        combine_clear<D, TS>(ckx[wave], cvx[wave], lane);
+        combine_clear<1, TS>(ckf[wave][0], cvf[wave][0], lane);
+        combine_clear<1, TS>(ckf[wave][1], cvf[wave][1], lane);
+        wave_sync();
         CellIdx<F_ELAST, D, FD> ix;
         CellRaw<F_ELAST, D, FD> raw;
         load_idx<F_ELAST, D, FD>(A.L, cell, ix);
@@ -318,17 +331,19 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
             }
             S += mu * mub + lm * lmb;
             if constexpr (FD > 0) {
-                if (A.grad_f0) {
+                if (A.grad_f0 && valid) {
                     const int64_t i0 = A.L.f0.map ? (int64_t)A.L.f0.map[cell * NF + r] : cell * NF + r;
-                    atomicAdd(A.grad_f0 + i0, A.seed * mub);
+                    const double x = A.seed * mub;
+                    combine_add<1, TS>(ckf[wave][0], cvf[wave][0], (unsigned long long)i0, &x, A.grad_f0);
                 }
-                if (A.grad_f1) {
+                if (A.grad_f1 && valid) {
                     const int64_t i1 = A.L.f1.map ? (int64_t)A.L.f1.map[cell * NF + r] : cell * NF + r;
-                    atomicAdd(A.grad_f1 + i1, A.seed * lmb);
+                    const double x = A.seed * lmb;
+                    combine_add<1, TS>(ckf[wave][1], cvf[wave][1], (unsigned long long)i1, &x, A.grad_f1);
                 }
             }
         }
-        if (A.cell_value) A.cell_value[cell] = S;
+        if (A.cell_value && valid) A.cell_value[cell] = S;
         // chain to the coordinates (as in k_adjoint_linear)
         double Jbar[D][D];
 #pragma unroll
@@ -343,16 +358,27 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
                 Jbar[i][j] = -t + S * K[j][i];
             }
         const double sd = A.seed;
+        if (valid) {
+            double vx[D + 1][D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            double x0 = 0.0;
+            for (int i = 0; i < D; ++i) {
+                double x0 = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                atomicAdd(A.grad_coords + (int64_t)ix.v[j + 1] * D + i, sd * Jbar[i][j]);
-                x0 -= Jbar[i][j];
+                for (int j = 0; j < D; ++j) {
+                    vx[j + 1][i] = sd * Jbar[i][j];
+                    x0 -= Jbar[i][j];
+                }
+                vx[0][i] = sd * x0;
             }
-            atomicAdd(A.grad_coords + (int64_t)ix.v[0] * D + i, sd * x0);
+#pragma unroll
+            for (int v = 0; v <= D; ++v)
+                combine_add<D, TS>(ckx[wave], cvx[wave], (unsigned long long)ix.v[v], vx[v], A.grad_coords);
         }
+        wave_sync();
+        combine_flush<D, TS>(ckx[wave], cvx[wave], A.grad_coords, lane);
+        if (A.grad_f0) combine_flush<1, TS>(ckf[wave][0], cvf[wave][0], A.grad_f0, lane);
+        if (A.grad_f1) combine_flush<1, TS>(ckf[wave][1], cvf[wave][1], A.grad_f1, lane);
+        wave_sync();
     }
 }
 

@@ -527,5 +527,51 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Per-wave combining of scatter-adds of NV values per key: the lanes insert
+// (key, values) into an open-addressing table in LDS, equal keys are summed
+// there, and each distinct key then goes to global memory as one atomic add
+// per value (cells that share a dof are neighbours, so a wave's 64 cells hold
+// far fewer distinct dofs than dof references). A key that finds no slot
+// within the probe limit is added to global memory directly.
+constexpr unsigned long long kEmptyKey = ~0ull;
+
+template <int NV, int TS>
+__device__ inline void combine_clear(unsigned long long* keys, double* vals, int lane) {
+    for (int i = lane; i < TS; i += 64) {
+        keys[i] = kEmptyKey;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) vals[i * NV + c] = 0.0;
+    }
+}
+
+template <int NV, int TS>
+__device__ inline void combine_add(unsigned long long* keys, double* vals, unsigned long long key, const double* v,
+                                   double* global_base) {
+    unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 40) & (TS - 1);
+    for (int t = 0; t < 32; ++t) {
+        const unsigned long long old = atomicCAS(&keys[h], kEmptyKey, key);
+        if (old == kEmptyKey || old == key) {
+#pragma unroll
+            for (int c = 0; c < NV; ++c) atomicAdd(&vals[h * NV + c], v[c]);
+            return;
+        }
+        h = (h + 1) & (TS - 1);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) atomicAdd(global_base + key * NV + c, v[c]);
+}
+
+template <int NV, int TS>
+__device__ inline void combine_flush(const unsigned long long* keys, const double* vals, double* global_base,
+                                     int lane) {
+    for (int i = lane; i < TS; i += 64) {
+        const unsigned long long key = keys[i];
+        if (key == kEmptyKey) continue;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) atomicAdd(global_base + key * NV + c, vals[i * NV + c]);
+    }
+}
+
+
 }  // namespace dev
 }  // namespace coffee

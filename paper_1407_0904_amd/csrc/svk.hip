@@ -304,15 +304,27 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
     }
 }
 
-// Residual with scatter of seed * b_e into grad_u (the energy's u-gradient).
+// Residual with scatter of seed * b_e into grad_u (the energy's u-gradient),
+// combined per wave.
 template <int D, int P, int NQ>
-__global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
+__global__ __launch_bounds__(256, 2) void k_svk_residual_scatter(SvkArgs A) {
     constexpr int NS = nsc(D, P);
     // every table read below has the same address in all lanes: scalar path
     const double* W = A.tab;
     const double* dphi = A.tab + NQ;
-    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.ncells;
-         cell += (int64_t)gridDim.x * blockDim.x) {
+    constexpr int TS = 512;  // table slots per wave
+    __shared__ unsigned long long ckeys[4][TS];
+    __shared__ double cvals[4][TS * D];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned long long* keys = ckeys[wave];
+    double* vals = cvals[wave];
+    // wave-uniform loop: every lane takes part in the table's clear and flush
+    for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) - lane; base < A.ncells;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cell = base + lane < A.ncells ? base + lane : A.ncells - 1;
+        const bool valid = base + lane < A.ncells;
+        combine_clear<D, TS>(keys, vals, lane);
+        wave_sync();
         Geom<D> g;
         double uv[NS * D];
         int vid[D + 1], uid[NS];
@@ -346,12 +358,19 @@ __global__ __launch_bounds__(256) void k_svk_residual_scatter(SvkArgs A) {
                 }
         }
         const double f = A.seed * g.adet;
+        if (valid) {
 #pragma unroll
-        for (int r = 0; r < NS; ++r) {
-            const int64_t base = A.u.map ? (int64_t)uid[r] * D : (cell * NS + r) * D;
+            for (int r = 0; r < NS; ++r) {
+                const unsigned long long key = A.u.map ? (unsigned long long)uid[r] : (unsigned long long)(cell * NS + r);
+                double v[D];
 #pragma unroll
-            for (int c = 0; c < D; ++c) atomicAdd(A.grad_u + base + c, f * res[c * NS + r]);
+                for (int c = 0; c < D; ++c) v[c] = f * res[c * NS + r];
+                combine_add<D, TS>(keys, vals, key, v, A.grad_u);
+            }
         }
+        wave_sync();
+        combine_flush<D, TS>(keys, vals, A.grad_u, lane);
+        wave_sync();
     }
 }
 
