@@ -187,8 +187,20 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
     // every table read below has the same address in all lanes: scalar path
     const double* W = A.tab;
     const double* dphi = A.tab + NQ;
-    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.ncells;
-         cell += (int64_t)gridDim.x * blockDim.x) {
+    // reverse pass: the vertex-coordinate scatter-adds are combined per wave
+    constexpr int TS = MODE == 2 ? 256 : 1;
+    __shared__ unsigned long long ckeys[4][TS];
+    __shared__ double cvals[4][TS * D];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wave-uniform loop (every lane takes part in the table's clear and flush)
+    for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) - lane; base < A.ncells;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const bool valid = base + lane < A.ncells;
+        const int64_t cell = valid ? base + lane : A.ncells - 1;
+        if constexpr (MODE == 2) {
+            combine_clear<D, TS>(ckeys[wave], cvals[wave], lane);
+            wave_sync();
+        }
         Geom<D> g;
         double uv[NS * D];
         int vid[D + 1], uid[NS];
@@ -264,14 +276,16 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
         }
         const double ad = g.adet;
         if constexpr (MODE == 0) {
-            reinterpret_cast<OT*>(A.out)[cell] = (OT)(ad * energy);
+            if (valid) reinterpret_cast<OT*>(A.out)[cell] = (OT)(ad * energy);
         } else if constexpr (MODE == 1) {
             OT* o = reinterpret_cast<OT*>(A.out) + cell * (D * NS);
+            if (valid) {
 #pragma unroll
-            for (int i = 0; i < D * NS; ++i) o[i] = (OT)(ad * res[i]);
+                for (int i = 0; i < D * NS; ++i) o[i] = (OT)(ad * res[i]);
+            }
         } else {
             const double Pi = ad * energy;
-            if (A.cell_value) A.cell_value[cell] = Pi;
+            if (A.cell_value && valid) A.cell_value[cell] = Pi;
             // Kbar scaled by |det J|; d Pi/d|det J| |det J| = Pi
 #pragma unroll
             for (int i = 0; i < D; ++i)
@@ -290,16 +304,25 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
                     Jbar[i][j] = -s + Pi * g.K[j][i];
                 }
             const double sd = A.seed;
+            if (valid) {
+                double vx[D + 1][D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                double x0 = 0.0;
+                for (int i = 0; i < D; ++i) {
+                    double x0 = 0.0;
 #pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    atomicAdd(A.grad_coords + (int64_t)vid[j + 1] * D + i, sd * Jbar[i][j]);
-                    x0 -= Jbar[i][j];
+                    for (int j = 0; j < D; ++j) {
+                        vx[j + 1][i] = sd * Jbar[i][j];
+                        x0 -= Jbar[i][j];
+                    }
+                    vx[0][i] = sd * x0;
                 }
-                atomicAdd(A.grad_coords + (int64_t)vid[0] * D + i, sd * x0);
+#pragma unroll
+                for (int v = 0; v <= D; ++v)
+                    combine_add<D, TS>(ckeys[wave], cvals[wave], (unsigned long long)vid[v], vx[v], A.grad_coords);
             }
+            wave_sync();
+            combine_flush<D, TS>(ckeys[wave], cvals[wave], A.grad_coords, lane);
+            wave_sync();
         }
     }
 }
