@@ -125,8 +125,22 @@ __global__ __launch_bounds__(256) void k_adjoint_linear(AdjArgs A) {
         __syncthreads();
         Rs = sR;
     }
-    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < A.L.ncells;
-         cell += (int64_t)gridDim.x * blockDim.x) {
+    // per-wave combining of the gradient scatter-adds (vertex coordinates and
+    // the fields' dofs)
+    constexpr int TS = 128;
+    constexpr int W0 = Dirs::N0 > 0 ? Dirs::WC : 1;
+    __shared__ unsigned long long ckx[4][TS], ck0[4][TS], ck1[4][TS];
+    __shared__ double cvx[4][TS * D], cv0[4][TS * W0], cv1[4][TS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wave-uniform loop: every lane takes part in the tables' clear and flush
+    for (int64_t wbase = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) - lane; wbase < A.L.ncells;
+         wbase += (int64_t)gridDim.x * blockDim.x) {
+        const bool valid = wbase + lane < A.L.ncells;
+        const int64_t cell = valid ? wbase + lane : A.L.ncells - 1;
+        combine_clear<D, TS>(ckx[wave], cvx[wave], lane);
+        if constexpr (Dirs::N0 > 0) combine_clear<W0, TS>(ck0[wave], cv0[wave], lane);
+        if constexpr (Dirs::N1 > 0) combine_clear<1, TS>(ck1[wave], cv1[wave], lane);
+        wave_sync();
         CellIdx<FORM, D, FD> ix;
         CellRaw<FORM, D, FD> raw;
         load_idx<FORM, D, FD>(A.L, cell, ix);
@@ -146,7 +160,7 @@ __global__ __launch_bounds__(256) void k_adjoint_linear(AdjArgs A) {
 #pragma unroll
         for (int r = 0; r < (Dirs::N1 > 0 ? Dirs::N1 : 1); ++r) f1bar[r] = 0.0;
         adjoint_blocks<FORM, D, P, FD, NC * NC>(A, Rs, cd, lam, u, S, Kbar, f0bar, f1bar);
-        if (A.cell_value) A.cell_value[cell] = S;
+        if (A.cell_value && valid) A.cell_value[cell] = S;
 
         // chain to the coordinates
         const auto& K = cd.g.K;
@@ -165,37 +179,55 @@ __global__ __launch_bounds__(256) void k_adjoint_linear(AdjArgs A) {
                 Jbar[i][j] = -s + adbar_ad * K[j][i];
             }
         const double sd = A.seed;
+        if (valid) {
+            double vx[D + 1][D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            double x0 = 0.0;
+            for (int i = 0; i < D; ++i) {
+                double x0 = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                atomicAdd(A.grad_coords + (int64_t)ix.v[j + 1] * D + i, sd * Jbar[i][j]);
-                x0 -= Jbar[i][j];
+                for (int j = 0; j < D; ++j) {
+                    vx[j + 1][i] = sd * Jbar[i][j];
+                    x0 -= Jbar[i][j];
+                }
+                vx[0][i] = sd * x0;
             }
-            atomicAdd(A.grad_coords + (int64_t)ix.v[0] * D + i, sd * x0);
-        }
-        if constexpr (Dirs::N0 > 0) {
-            if (A.grad_f0) {
-                constexpr int NF = Dirs::NF, WC = Dirs::WC;
 #pragma unroll
-                for (int r = 0; r < NF; ++r) {
-                    const int64_t base = A.L.f0.map ? (int64_t)ix.f0[r] * WC : (cell * NF + r) * WC;
+            for (int v = 0; v <= D; ++v)
+                combine_add<D, TS>(ckx[wave], cvx[wave], (unsigned long long)ix.v[v], vx[v], A.grad_coords);
+            if constexpr (Dirs::N0 > 0) {
+                if (A.grad_f0) {
+                    constexpr int NF = Dirs::NF;
 #pragma unroll
-                    for (int c = 0; c < WC; ++c) atomicAdd(A.grad_f0 + base + c, sd * f0bar[r * WC + c]);
+                    for (int r = 0; r < NF; ++r) {
+                        const int64_t key = A.L.f0.map ? (int64_t)ix.f0[r] : cell * NF + r;
+                        double v[W0];
+#pragma unroll
+                        for (int c = 0; c < W0; ++c) v[c] = sd * f0bar[r * W0 + c];
+                        combine_add<W0, TS>(ck0[wave], cv0[wave], (unsigned long long)key, v, A.grad_f0);
+                    }
                 }
             }
+            if constexpr (Dirs::N1 > 0) {
+                if (A.grad_f1) {
+                    constexpr int NF = Dirs::NF;
+#pragma unroll
+                    for (int r = 0; r < NF; ++r) {
+                        const int64_t key = A.L.f1.map ? (int64_t)ix.f1[r] : cell * NF + r;
+                        const double v = sd * f1bar[r];
+                        combine_add<1, TS>(ck1[wave], cv1[wave], (unsigned long long)key, &v, A.grad_f1);
+                    }
+                }
+            }
+        }
+        wave_sync();
+        combine_flush<D, TS>(ckx[wave], cvx[wave], A.grad_coords, lane);
+        if constexpr (Dirs::N0 > 0) {
+            if (A.grad_f0) combine_flush<W0, TS>(ck0[wave], cv0[wave], A.grad_f0, lane);
         }
         if constexpr (Dirs::N1 > 0) {
-            if (A.grad_f1) {
-                constexpr int NF = Dirs::NF;
-#pragma unroll
-                for (int r = 0; r < NF; ++r) {
-                    const int64_t base = A.L.f1.map ? (int64_t)ix.f1[r] : cell * NF + r;
-                    atomicAdd(A.grad_f1 + base, sd * f1bar[r]);
-                }
-            }
+            if (A.grad_f1) combine_flush<1, TS>(ck1[wave], cv1[wave], A.grad_f1, lane);
         }
+        wave_sync();
     }
 }
 
