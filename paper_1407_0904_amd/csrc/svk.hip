@@ -180,7 +180,8 @@ typedef unsigned int svk_u32x4 __attribute__((ext_vector_type(4)));
 template <int D, int P>
 constexpr int svk_tab_elems(int nq) { return nq + D * nq * nsc(D, P); }
 
-// MODE 0: energy, 1: residual, 2: reverse pass of the energy.
+// MODE 0: energy, 1: residual, 2: reverse pass of the energy (coordinates),
+// 3: the reverse pass with the displacement gradient (the residual) too.
 template <int D, int P, int NQ, int MODE, typename OT>
 __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
     constexpr int NS = nsc(D, P);
@@ -188,17 +189,21 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
     const double* W = A.tab;
     const double* dphi = A.tab + NQ;
     // reverse pass: the vertex-coordinate scatter-adds are combined per wave
-    constexpr int TS = MODE == 2 ? 256 : 1;
-    __shared__ unsigned long long ckeys[4][TS];
-    __shared__ double cvals[4][TS * D];
+    constexpr bool REV = MODE >= 2;                 // reverse pass
+    constexpr bool RES = MODE == 1 || MODE == 3;    // residual (MODE 3: scattered into grad_u)
+    constexpr int TS = REV ? 256 : 1;
+    constexpr int TU = MODE == 3 ? 256 : 1;
+    __shared__ unsigned long long ckeys[4][TS], ukeys[4][TU];
+    __shared__ double cvals[4][TS * D], uvals[4][TU * D];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // wave-uniform loop (every lane takes part in the table's clear and flush)
     for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) - lane; base < A.ncells;
          base += (int64_t)gridDim.x * blockDim.x) {
         const bool valid = base + lane < A.ncells;
         const int64_t cell = valid ? base + lane : A.ncells - 1;
-        if constexpr (MODE == 2) {
+        if constexpr (REV) {
             combine_clear<D, TS>(ckeys[wave], cvals[wave], lane);
+            if constexpr (MODE == 3) combine_clear<D, TU>(ukeys[wave], uvals[wave], lane);
             wave_sync();
         }
         Geom<D> g;
@@ -206,13 +211,13 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
         int vid[D + 1], uid[NS];
         svk_load<D, NS>(A, cell, g, uv, vid, uid);
         double energy = 0.0;
-        double res[MODE == 1 ? D * NS : 1];
+        double res[RES ? D * NS : 1];
         double Kbar[D][D];  // reverse pass: d Pi / d K
-        if constexpr (MODE == 1) {
+        if constexpr (RES) {
 #pragma unroll
             for (int i = 0; i < D * NS; ++i) res[i] = 0.0;
         }
-        if constexpr (MODE == 2) {
+        if constexpr (REV) {
 #pragma unroll
             for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
             svk_point<D, NS, true>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, &psi, Pm);
             const double wq = cload(W + q);
             energy += wq * psi;
-            if constexpr (MODE == 1) {
+            if constexpr (RES) {
                 // b_(c,a) += w sum_al (P K^T)_c,al dphi_a/dX_al
                 double Q[D][D];
 #pragma unroll
@@ -251,7 +256,7 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
                     }
                 }
             }
-            if constexpr (MODE == 2) {
+            if constexpr (REV) {
                 // d Pi / d K[al][j] = |det J| sum_q w sum_i P_ij U_i,al
                 double U[D][D];
 #pragma unroll
@@ -319,81 +324,25 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
 #pragma unroll
                 for (int v = 0; v <= D; ++v)
                     combine_add<D, TS>(ckeys[wave], cvals[wave], (unsigned long long)vid[v], vx[v], A.grad_coords);
+                if constexpr (MODE == 3) {
+                    // seed * residual into grad_u
+                    const double f = sd * ad;
+#pragma unroll
+                    for (int r = 0; r < NS; ++r) {
+                        const unsigned long long key =
+                            A.u.map ? (unsigned long long)uid[r] : (unsigned long long)(cell * NS + r);
+                        double v[D];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) v[c] = f * res[c * NS + r];
+                        combine_add<D, TU>(ukeys[wave], uvals[wave], key, v, A.grad_u);
+                    }
+                }
             }
             wave_sync();
             combine_flush<D, TS>(ckeys[wave], cvals[wave], A.grad_coords, lane);
+            if constexpr (MODE == 3) combine_flush<D, TU>(ukeys[wave], uvals[wave], A.grad_u, lane);
             wave_sync();
         }
-    }
-}
-
-// Residual with scatter of seed * b_e into grad_u (the energy's u-gradient),
-// combined per wave.
-template <int D, int P, int NQ>
-__global__ __launch_bounds__(256, 2) void k_svk_residual_scatter(SvkArgs A) {
-    constexpr int NS = nsc(D, P);
-    // every table read below has the same address in all lanes: scalar path
-    const double* W = A.tab;
-    const double* dphi = A.tab + NQ;
-    constexpr int TS = 512;  // table slots per wave
-    __shared__ unsigned long long ckeys[4][TS];
-    __shared__ double cvals[4][TS * D];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    unsigned long long* keys = ckeys[wave];
-    double* vals = cvals[wave];
-    // wave-uniform loop: every lane takes part in the table's clear and flush
-    for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) - lane; base < A.ncells;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t cell = base + lane < A.ncells ? base + lane : A.ncells - 1;
-        const bool valid = base + lane < A.ncells;
-        combine_clear<D, TS>(keys, vals, lane);
-        wave_sync();
-        Geom<D> g;
-        double uv[NS * D];
-        int vid[D + 1], uid[NS];
-        svk_load<D, NS>(A, cell, g, uv, vid, uid);
-        double res[D * NS];
-#pragma unroll
-        for (int i = 0; i < D * NS; ++i) res[i] = 0.0;
-#pragma unroll 1
-        for (int q = 0; q < NQ; ++q) {
-            SvkPoint<D> pt;
-            double Pm[D][D];
-            svk_point<D, NS, true>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, nullptr, Pm);
-            double Q[D][D];
-#pragma unroll
-            for (int c = 0; c < D; ++c)
-#pragma unroll
-                for (int al = 0; al < D; ++al) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) t += Pm[c][j] * g.K[al][j];
-                    Q[c][al] = cload(W + q) * t;
-                }
-#pragma unroll
-            for (int a = 0; a < NS; ++a)
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int al = 0; al < D; ++al) t += Q[c][al] * cload(dphi + (size_t)al * NQ * NS + q * NS + a);
-                    res[c * NS + a] += t;
-                }
-        }
-        const double f = A.seed * g.adet;
-        if (valid) {
-#pragma unroll
-            for (int r = 0; r < NS; ++r) {
-                const unsigned long long key = A.u.map ? (unsigned long long)uid[r] : (unsigned long long)(cell * NS + r);
-                double v[D];
-#pragma unroll
-                for (int c = 0; c < D; ++c) v[c] = f * res[c * NS + r];
-                combine_add<D, TS>(keys, vals, key, v, A.grad_u);
-            }
-        }
-        wave_sync();
-        combine_flush<D, TS>(keys, vals, A.grad_u, lane);
-        wave_sync();
     }
 }
 
@@ -684,8 +633,8 @@ hipError_t launch_svk(int form, int precision, const dev::SvkArgs& a, hipStream_
     const int64_t blocks = (a.ncells + 255) / 256;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)ncu * 8));
     if (reverse) {
-        hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 2, double>), dim3(grid), dim3(256), 0, s, a);
-        if (a.grad_u) hipLaunchKernelGGL((dev::k_svk_residual_scatter<D, P, NQ>), dim3(grid), dim3(256), 0, s, a);
+        if (a.grad_u) hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 3, double>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 2, double>), dim3(grid), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     const bool f64 = precision == COFFEE_FP64;
