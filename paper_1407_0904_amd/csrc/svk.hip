@@ -15,13 +15,16 @@
 // dphi_b/dX_b with H = w |det J| K C K^T, accumulated as two rank-structured
 // updates per point and reference direction.
 //
-// Work layout: energy and residual one thread per cell. Jacobian: a wave takes
-// a few consecutive cells; F at each (cell, point) is formed once into LDS,
-// then each lane accumulates a slice of rows of one block c <= c' (the mirrored
-// block comes from the same values: the Jacobian is symmetric), and each cell's
-// tensor is staged in LDS and written as contiguous 16-byte stores. Reference
-// gradients and weights are read at wave-uniform addresses through the scalar
-// path (staged in LDS where the Jacobian's lanes read different rows).
+// Work layout: energy, residual and the energy's reverse pass one thread per
+// cell (the reverse pass also scatters the residual into the displacement
+// gradient, and combines its scatter-adds per wave in LDS). Jacobian: a wave
+// takes a few consecutive cells; F and K S K^T at each (cell, point) are formed
+// once into LDS, then each lane accumulates a slice of rows of one block
+// c <= c' (the mirrored block comes from the same values: the Jacobian is
+// symmetric), and the cells' tensors are staged in LDS and written as
+// contiguous 16-byte stores. Reference gradients and weights are read at
+// wave-uniform addresses through the scalar path (staged in LDS where the
+// Jacobian's lanes read different rows).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -188,7 +191,8 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
     // every table read below has the same address in all lanes: scalar path
     const double* W = A.tab;
     const double* dphi = A.tab + NQ;
-    // reverse pass: the vertex-coordinate scatter-adds are combined per wave
+    // reverse pass: the scatter-adds (vertex coordinates; MODE 3 also the
+    // displacement dofs) are combined per wave
     constexpr bool REV = MODE >= 2;                 // reverse pass
     constexpr bool RES = MODE == 1 || MODE == 3;    // residual (MODE 3: scattered into grad_u)
     constexpr int TS = REV ? 256 : 1;
