@@ -108,6 +108,52 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+# Shape checks. They run before any device pointer is taken, so a wrong shape
+# is a ValueError on the host instead of an out-of-bounds access on the GPU.
+def _nloc(d: int, p: int) -> int:
+    return (p + 1) * (p + 2) // 2 if d == 2 else (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def _need(t, name, dtype, shape=None, numel=None, allow_none=False):
+    if t is None:
+        if allow_none:
+            return
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def _check_mesh(d, coords, cell_to_vertex, where=""):
+    _need(coords, where + "coords", torch.float64)
+    _need(cell_to_vertex, where + "cell_to_vertex", torch.int32)
+    if coords.ndim != 2 or coords.shape[1] != d:
+        raise ValueError(f"{where}coords has shape {tuple(coords.shape)}, expected (nvert, {d})")
+    if cell_to_vertex.ndim != 2 or cell_to_vertex.shape[1] != d + 1:
+        raise ValueError(f"{where}cell_to_vertex has shape {tuple(cell_to_vertex.shape)}, expected (ncells, {d + 1})")
+
+
+def _check_fields(coeffs, d, ncells, where="coeffs"):
+    for i, f in enumerate(coeffs):
+        name = f"{where}[{i}]"
+        _need(f.values, name + ".values", torch.float64)
+        if not 1 <= int(f.degree) <= 4 or int(f.ncomp) < 1:
+            continue  # the library reports the bad degree or component count
+        nloc, nc = _nloc(d, int(f.degree)), int(f.ncomp)
+        if f.cell_to_dof is not None:
+            _need(f.cell_to_dof, name + ".cell_to_dof", torch.int32, shape=(ncells, nloc))
+            v = f.values
+            if v.numel() % nc or (v.ndim >= 2 and v.shape[-1] != nc) or (v.ndim == 1 and nc != 1):
+                raise ValueError(f"{name}.values has shape {tuple(v.shape)}, expected (ndofs, {nc})")
+        else:
+            _need(f.values, name + ".values", torch.float64, numel=ncells * nloc * nc)
+
+
 @dataclass
 class DeviceField:
     """A coefficient field on the device (see coffee_field in coffee.h)."""
@@ -164,10 +210,17 @@ def coffee_assemble(form, cell, degree: int, coords: torch.Tensor, cell_to_verte
                     out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Element tensors of every cell (coffee_assemble)."""
     c = CELLS[cell]
+    _check_mesh(c, coords, cell_to_vertex)
     ncells = cell_to_vertex.shape[0]
+    _check_fields(coeffs, c, ncells)
     odt = torch.float64 if precision == "fp64" else torch.float32
-    if out is None:
-        out = torch.empty(output_shape(form, ncells, c, degree), dtype=odt, device=coords.device)
+    shape = output_shape(form, ncells, c, degree)
+    if min(shape) < 0:  # bad form or degree: the library reports it
+        out = torch.empty(0, dtype=odt, device=coords.device) if out is None else out
+    elif out is None:
+        out = torch.empty(shape, dtype=odt, device=coords.device)
+    else:
+        _need(out, "out", odt, numel=int(np.prod(shape)))
     cst = np.ascontiguousarray(constants, dtype=np.float64)
     st = _lib.coffee_assemble(FORMS[form], c, degree, quad_degree, PRECISIONS[precision],
                               _dptr(coords, torch.float64, "coords"), coords.shape[0] if coords.ndim else 0,
@@ -185,11 +238,23 @@ def coffee_assemble_adjoint(form, cell, degree: int, coords, cell_to_vertex, coe
                             workspace=None, stream=None):
     """Accumulates seed * dS/d(coords, coefficient values); returns (grad_coords, grad_coeffs)."""
     c = CELLS[cell]
+    _check_mesh(c, coords, cell_to_vertex)
     ncells = cell_to_vertex.shape[0]
+    _check_fields(coeffs, c, ncells)
+    N = coffee_tensor_dim(form, c, degree)
+    if N > 0:
+        _need(lam, "lam", torch.float64, shape=(ncells, N), allow_none=True)
+        _need(u, "u", torch.float64, shape=(ncells, N), allow_none=True)
+    _need(cell_value, "cell_value", torch.float64, numel=ncells, allow_none=True)
     if grad_coords is None:
         grad_coords = torch.zeros_like(coords)
+    _need(grad_coords, "grad_coords", torch.float64, shape=tuple(coords.shape))
     if grad_coeffs is None:
         grad_coeffs = [torch.zeros_like(f.values) for f in coeffs]
+    if len(grad_coeffs) != len(coeffs):
+        raise ValueError(f"grad_coeffs has {len(grad_coeffs)} entries, expected {len(coeffs)}")
+    for i, (g, f) in enumerate(zip(grad_coeffs, coeffs)):
+        _need(g, f"grad_coeffs[{i}]", torch.float64, shape=tuple(f.values.shape), allow_none=True)
     gptr = (C.c_void_p * max(1, len(coeffs)))(
         *[_dptr(g, torch.float64, "grad_coeffs", allow_none=True) for g in grad_coeffs])
     fa = _fields(list(coeffs))
@@ -230,6 +295,26 @@ def coffee_batch_workspace_size(nseg: int, nentries: int) -> int:
     return int(_lib.coffee_batch_workspace_size(int(nseg), int(nentries)))
 
 
+def _check_batch(segments, seg_of, cell_of, out_offset, out, odt, total_elems, workspace):
+    for i, sg in enumerate(segments):
+        d = CELLS[sg.cell]
+        _check_mesh(d, sg.coords, sg.cell_to_vertex, where=f"segments[{i}].")
+        _check_fields([sg.coeff], d, sg.cell_to_vertex.shape[0], where=f"segments[{i}].coeff")
+    _need(seg_of, "seg_of", torch.int32)
+    if seg_of.ndim != 1:
+        raise ValueError(f"seg_of has shape {tuple(seg_of.shape)}, expected (nentries,)")
+    n = seg_of.shape[0]
+    _need(cell_of, "cell_of", torch.int64, shape=(n,))
+    _need(out_offset, "out_offset", torch.int64, shape=(n,))
+    _need(out, "out", odt)
+    if out.numel() < total_elems:
+        raise ValueError(f"out has {out.numel()} elements, fewer than total_elems = {total_elems}")
+    need = coffee_batch_workspace_size(len(segments), n)
+    _need(workspace, "workspace", torch.uint8)
+    if workspace.numel() < need:
+        raise ValueError(f"workspace has {workspace.numel()} bytes, expected at least {need}")
+
+
 def _segments(segments):
     segs = (_Segment * len(segments))()
     fields = (_Field * len(segments))()
@@ -256,6 +341,7 @@ def coffee_assemble_batch(segments, seg_of: torch.Tensor, cell_of: torch.Tensor,
         out = torch.empty(total_elems, dtype=odt, device=dev)
     if workspace is None:
         workspace = torch.empty(coffee_batch_workspace_size(len(segments), n), dtype=torch.uint8, device=dev)
+    _check_batch(segments, seg_of, cell_of, out_offset, out, odt, total_elems, workspace)
     segs, _keep = _segments(segments)
     st = _lib.coffee_assemble_batch(PRECISIONS[precision], segs, len(segments),
                                     _dptr(seg_of, torch.int32, "seg_of"), _dptr(cell_of, torch.int64, "cell_of"),
@@ -280,6 +366,7 @@ def coffee_assemble_batch_packed(segments, seg_of: torch.Tensor, cell_of: torch.
         out_offset = torch.empty(n, dtype=torch.int64, device=dev)
     if workspace is None:
         workspace = torch.empty(coffee_batch_workspace_size(len(segments), n), dtype=torch.uint8, device=dev)
+    _check_batch(segments, seg_of, cell_of, out_offset, out, odt, total_elems, workspace)
     segs, _keep = _segments(segments)
     st = _lib.coffee_assemble_batch_packed(PRECISIONS[precision], segs, len(segments),
                                            _dptr(seg_of, torch.int32, "seg_of"),
@@ -292,6 +379,7 @@ def coffee_assemble_batch_packed(segments, seg_of: torch.Tensor, cell_of: torch.
 
 def coffee_check_geometry(cell, coords, cell_to_vertex, stream=None) -> int:
     """Smallest bad cell index (det J <= 0 or non-finite), or -1."""
+    _check_mesh(CELLS[cell], coords, cell_to_vertex)
     fb = torch.empty(1, dtype=torch.int64, device=coords.device)
     st = _lib.coffee_check_geometry(CELLS[cell], _dptr(coords, torch.float64, "coords"), coords.shape[0],
                                     _dptr(cell_to_vertex, torch.int32, "cell_to_vertex"),

@@ -43,6 +43,7 @@ constexpr int kScanThreads = 1024;  // k_bin_scan: kMaxSlices / kScanThreads sli
 struct BinDesc {
     const double* coords;
     const int32_t* c2v;
+    int64_t ncells;     // cells of the bin's mesh (entries outside are skipped)
     FieldArg f0;
     const void* rfrag;
     const double* r64;  // degree-1 bins: the FP64 reference tensor [K][n*n]
@@ -77,13 +78,25 @@ struct BatchArgs {
 
 // ---------------------------------------------------------------- binning
 
+// Bin of entry i, or -1 for an entry whose segment id or cell index is out of
+// range (such entries are skipped: nothing is read or written for them).
+__device__ inline int entry_bin(const BatchArgs& A, int64_t i) {
+    const int s = A.seg_of[i];
+    if (s < 0 || s >= A.nbins) return -1;
+    const int64_t c = A.cell_of[i];
+    return (c >= 0 && c < A.bins[s].ncells) ? s : -1;
+}
+
 __global__ __launch_bounds__(256) void k_bin_count(BatchArgs A) {
     __shared__ unsigned int h[kMaxBins];
     if (threadIdx.x < kMaxBins) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t s0 = blockIdx.x * A.slice;
     const int64_t s1 = s0 + A.slice < A.nentries ? s0 + A.slice : A.nentries;
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) atomicAdd(&h[A.seg_of[i]], 1u);
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        const int b = entry_bin(A, i);
+        if (b >= 0) atomicAdd(&h[b], 1u);
+    }
     __syncthreads();
     if (threadIdx.x < kMaxBins) A.scnt[blockIdx.x * kMaxBins + threadIdx.x] = h[threadIdx.x];
     if (blockIdx.x == 0) {
@@ -160,7 +173,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A) {
     for (int64_t i0 = s0; i0 < s1; i0 += 256) {
         const int64_t i = i0 + t;
         const bool valid = i < s1;
-        const int b = valid ? A.seg_of[i] : -1;
+        const int b = valid ? entry_bin(A, i) : -1;
         int rank = 0;
         for (int bb = 0; bb < A.nbins; ++bb) {
             const unsigned long long m = __ballot(b == bb);
@@ -168,7 +181,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(BatchArgs A) {
             if (lane == 0) wtot[w][bb] = (unsigned int)__popcll(m);
         }
         __syncthreads();
-        if (valid) {
+        if (valid && b < 0 && A.packed) A.out_offset_w[i] = -1;  // skipped entry
+        if (b >= 0) {
             unsigned long long pos = cur[b] + rank;
             for (int ww = 0; ww < w; ++ww) pos += wtot[ww][b];
             A.bcell[pos] = (int32_t)A.cell_of[i];
@@ -709,6 +723,7 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
         dev::BinDesc& d = a.bins[b];
         d.coords = s.coords;
         d.c2v = s.cell_to_vertex;
+        d.ncells = s.ncells_mesh;
         d.f0 = dev::FieldArg{s.coeff->values, s.coeff->cell_to_dof};
         d.rfrag = rf;
         d.r64 = nullptr;

@@ -32,6 +32,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "library.h"
@@ -54,11 +55,6 @@ struct SvkArgs {
     double* grad_coords;
     double* grad_u;
     double* cell_value;
-};
-
-template <int D>
-struct SvkPoint {
-    double F[D][D], S[D][D];
 };
 
 // Reference-table read: through the scalar path when the address is the same
@@ -115,42 +111,66 @@ __device__ inline void svk_S(const double (&F)[D][D], double mu, double lm, doub
         for (int j = 0; j < D; ++j) S[i][j] = (i == j ? lm * trE : 0.0) + 2.0 * mu * E[i][j];
 }
 
-// F and S at point q from the reference displacement gradient.
-template <int D, int NS, bool SC = false>
-__device__ inline void svk_point(const double (&uv)[NS * D], const double (&K)[D][D], const double* dphi_q, int nq,
-                                 double mu, double lm, SvkPoint<D>& pt, double* psi, double (&Pout)[D][D]) {
-    svk_F<D, NS, SC>(uv, K, dphi_q, nq, pt.F);
-    double E[D][D], trE = 0.0;
+// F, S, psi and P at point q from the reference displacement gradient, in
+// the arithmetic type T (FP64, or FP32 for the FP32 energy and residual).
+// E is formed from the displacement gradient H = grad u as (H + H^T + H^T H)/2,
+// which equals (F^T F - I)/2 without the cancellation of F^T F against I.
+template <int D, int NS, bool SC = false, typename T = double>
+__device__ inline void svk_point(const T (&uv)[NS * D], const T (&K)[D][D], const double* dphi_q, int nq, T mu,
+                                 T lm, T (&F)[D][D], T* psi, T (&Pout)[D][D]) {
+    T U[D][D];  // U[i][a] = sum_r u_{r,i} dphi_r/dX_a
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T s = T(0);
+#pragma unroll
+            for (int r = 0; r < NS; ++r) s += uv[r * D + i] * (T)tread<SC>(dphi_q + (size_t)a * nq * NS + r);
+            U[i][a] = s;
+        }
+    T H[D][D];
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            double t = 0.0;
+            T g = T(0);
 #pragma unroll
-            for (int k = 0; k < D; ++k) t += pt.F[k][i] * pt.F[k][j];
-            E[i][j] = 0.5 * (t - (i == j ? 1.0 : 0.0));
+            for (int a = 0; a < D; ++a) g += U[i][a] * K[a][j];
+            H[i][j] = g;
+            F[i][j] = (i == j ? T(1) : T(0)) + g;
         }
-#pragma unroll
-    for (int i = 0; i < D; ++i) trE += E[i][i];
+    T E[D][D], trE = T(0);
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int j = 0; j < D; ++j) pt.S[i][j] = (i == j ? lm * trE : 0.0) + 2.0 * mu * E[i][j];
+        for (int j = 0; j < D; ++j) {
+            T t = H[i][j] + H[j][i];
+#pragma unroll
+            for (int k = 0; k < D; ++k) t += H[k][i] * H[k][j];
+            E[i][j] = T(0.5) * t;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) trE += E[i][i];
+    T S[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) S[i][j] = (i == j ? lm * trE : T(0)) + T(2) * mu * E[i][j];
     if (psi) {
-        double EE = 0.0;
+        T EE = T(0);
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
             for (int j = 0; j < D; ++j) EE += E[i][j] * E[i][j];
-        *psi = 0.5 * lm * trE * trE + mu * EE;
+        *psi = T(0.5) * lm * trE * trE + mu * EE;
     }
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            double t = 0.0;
+            T t = T(0);
 #pragma unroll
-            for (int k = 0; k < D; ++k) t += pt.F[i][k] * pt.S[k][j];
+            for (int k = 0; k < D; ++k) t += F[i][k] * S[k][j];
             Pout[i][j] = t;
         }
 }
@@ -188,6 +208,10 @@ constexpr int svk_tab_elems(int nq) { return nq + D * nq * nsc(D, P); }
 template <int D, int P, int NQ, int MODE, typename OT>
 __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
     constexpr int NS = nsc(D, P);
+    // arithmetic type of the point loop: the output type for the forward
+    // energy and residual (FP32 mode computes them in FP32 from the FP64
+    // geometry), FP64 for the reverse pass
+    using T = std::conditional_t<(MODE <= 1), OT, double>;
     // every table read below has the same address in all lanes: scalar path
     const double* W = A.tab;
     const double* dphi = A.tab + NQ;
@@ -211,15 +235,22 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
             wave_sync();
         }
         Geom<D> g;
-        double uv[NS * D];
+        double uvd[NS * D];
         int vid[D + 1], uid[NS];
-        svk_load<D, NS>(A, cell, g, uv, vid, uid);
-        double energy = 0.0;
-        double res[RES ? D * NS : 1];
+        svk_load<D, NS>(A, cell, g, uvd, vid, uid);
+        T uv[NS * D], K[D][D];
+#pragma unroll
+        for (int i = 0; i < NS * D; ++i) uv[i] = (T)uvd[i];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) K[i][j] = (T)g.K[i][j];
+        T energy = T(0);
+        T res[RES ? D * NS : 1];
         double Kbar[D][D];  // reverse pass: d Pi / d K
         if constexpr (RES) {
 #pragma unroll
-            for (int i = 0; i < D * NS; ++i) res[i] = 0.0;
+            for (int i = 0; i < D * NS; ++i) res[i] = T(0);
         }
         if constexpr (REV) {
 #pragma unroll
@@ -229,31 +260,30 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
         }
 #pragma unroll 1
         for (int q = 0; q < NQ; ++q) {
-            SvkPoint<D> pt;
-            double psi, Pm[D][D];
-            svk_point<D, NS, true>(uv, g.K, dphi + q * NS, NQ, A.mu, A.lambda, pt, &psi, Pm);
-            const double wq = cload(W + q);
+            T Fm[D][D], psi, Pm[D][D];
+            svk_point<D, NS, true, T>(uv, K, dphi + q * NS, NQ, (T)A.mu, (T)A.lambda, Fm, &psi, Pm);
+            const T wq = (T)cload(W + q);
             energy += wq * psi;
             if constexpr (RES) {
                 // b_(c,a) += w sum_al (P K^T)_c,al dphi_a/dX_al
-                double Q[D][D];
+                T Q[D][D];
 #pragma unroll
                 for (int c = 0; c < D; ++c)
 #pragma unroll
                     for (int al = 0; al < D; ++al) {
-                        double t = 0.0;
+                        T t = T(0);
 #pragma unroll
-                        for (int j = 0; j < D; ++j) t += Pm[c][j] * g.K[al][j];
+                        for (int j = 0; j < D; ++j) t += Pm[c][j] * K[al][j];
                         Q[c][al] = wq * t;
                     }
 #pragma unroll
                 for (int a = 0; a < NS; ++a) {
-                    double dp[D];
+                    T dp[D];
 #pragma unroll
-                    for (int al = 0; al < D; ++al) dp[al] = cload(dphi + (size_t)al * NQ * NS + q * NS + a);
+                    for (int al = 0; al < D; ++al) dp[al] = (T)cload(dphi + (size_t)al * NQ * NS + q * NS + a);
 #pragma unroll
                     for (int c = 0; c < D; ++c) {
-                        double t = 0.0;
+                        T t = T(0);
 #pragma unroll
                         for (int al = 0; al < D; ++al) t += Q[c][al] * dp[al];
                         res[c * NS + a] += t;
@@ -269,7 +299,7 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
                     for (int al = 0; al < D; ++al) {
                         double s = 0.0;
 #pragma unroll
-                        for (int r = 0; r < NS; ++r) s += uv[r * D + i] * cload(dphi + (size_t)al * NQ * NS + q * NS + r);
+                        for (int r = 0; r < NS; ++r) s += uvd[r * D + i] * cload(dphi + (size_t)al * NQ * NS + q * NS + r);
                         U[i][al] = s;
                     }
 #pragma unroll
@@ -285,12 +315,12 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
         }
         const double ad = g.adet;
         if constexpr (MODE == 0) {
-            if (valid) reinterpret_cast<OT*>(A.out)[cell] = (OT)(ad * energy);
+            if (valid) reinterpret_cast<OT*>(A.out)[cell] = (OT)((T)ad * energy);
         } else if constexpr (MODE == 1) {
             OT* o = reinterpret_cast<OT*>(A.out) + cell * (D * NS);
             if (valid) {
 #pragma unroll
-                for (int i = 0; i < D * NS; ++i) o[i] = (OT)(ad * res[i]);
+                for (int i = 0; i < D * NS; ++i) o[i] = (OT)((T)ad * res[i]);
             }
         } else {
             const double Pi = ad * energy;

@@ -113,3 +113,20 @@ def test_tuning_cache_parsing(lib, tmp_path):
     assert tuner.read_batch_costs(str(out)) == {("helmholtz", 3, 3, "fp32"): 1.5}
     assert tuner.read_batch_costs(str(out), "packed") == {("helmholtz", 3, 3, "fp32"): 1.25}
     assert f(None) == 0
+
+
+def test_batch_workspace_size_checked_on_host(lib):
+    """A workspace smaller than coffee_batch_workspace_size is reported
+    (status 3) before anything is read from the segment array or the device."""
+    lib.coffee_batch_workspace_size.restype = C.c_int64
+    lib.coffee_batch_workspace_size.argtypes = [C.c_int, C.c_int64]
+    need = lib.coffee_batch_workspace_size(1, 1000)
+    assert need >= 1000 * 12
+    for name in ("coffee_assemble_batch",):
+        f = getattr(lib, name)
+        f.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                      C.c_void_p, C.c_int64, C.c_void_p]
+        f.restype = C.c_int
+        dummy = C.c_void_p(16)  # never dereferenced
+        assert f(1, dummy, 1, dummy, dummy, dummy, 1000, dummy, dummy, need - 1, None) == 3
+        assert f(1, dummy, 17, dummy, dummy, dummy, 1000, dummy, dummy, need, None) == 1

@@ -115,3 +115,44 @@ def test_svk_jacobian_ragged_counts(cf, oracle, d, p):
             got = assemble_gpu("svk_jacobian", sub, p, [f], constants=cst, precision="fp64").cpu().numpy()
             err = cell_rel_err(got.reshape(count, -1), ref.reshape(count, -1))
             assert err < TOL["fp64"], (count, f.cell_to_dof is None, err)
+
+
+def test_svk_energy_adjoint_full_size_sampled(cf, oracle):
+    """196,608-cell SVK P2 tetrahedra: the energy's reverse pass over the whole
+    mesh. The gradient at sampled vertices and displacement dofs equals the
+    oracle's complex-step adjoint over the cells touching them; the whole
+    coordinate gradient is translation invariant; the displacement gradient
+    equals the assembled residual (R = dPi/du) scattered to the dofs."""
+    import torch
+    from gpu_util import to_dev
+    w = I.workload("svk_p2_tet")
+    mesh, u = w.mesh, w.fields[0]
+    coords, c2v, dfs = to_dev(mesh, w.fields)
+    cv = torch.empty(mesh.ncells, dtype=torch.float64, device=coords.device)
+    gc, gu = cf.coffee_assemble_adjoint("svk_energy", 3, 2, coords, c2v, coeffs=dfs, constants=w.constants,
+                                        seed=1.0, cell_value=cv)
+    res = cf.coffee_assemble("svk_residual", 3, 2, coords, c2v, coeffs=dfs, constants=w.constants)
+    torch.cuda.synchronize()
+    # residual [E, 3 * 10] (component-blocked) scattered to [ndofs, 3]
+    scat = torch.zeros_like(dfs[0].values)
+    rb = res.reshape(mesh.ncells, 3, 10).permute(0, 2, 1).reshape(-1, 3)
+    scat.index_add_(0, dfs[0].cell_to_dof.reshape(-1).long(), rb)
+    gc, gu, scat = gc.cpu().numpy(), gu[0].cpu().numpy(), scat.cpu().numpy()
+    assert np.max(np.abs(gu - scat)) < 1e-11 * np.max(np.abs(scat))
+    scale = np.max(np.abs(gc))
+    assert np.max(np.abs(gc.sum(axis=0))) < 1e-10 * scale * np.sqrt(mesh.nvert)
+    rng = np.random.default_rng(21)
+    for v in rng.integers(0, mesh.nvert, 5):
+        cells = np.nonzero(np.any(mesh.cells == v, axis=1))[0]
+        sub = I.Mesh(3, mesh.n, mesh.coords, mesh.cells[cells])
+        f = I.Field(u.values, u.cell_to_dof[cells], 2, 3)
+        _, gref, _ = oracle.adjoint("svk_energy", sub, 2, fields=[f], constants=w.constants)
+        np.testing.assert_allclose(gc[v], gref[v], rtol=1e-9, atol=1e-10 * np.max(np.abs(gref[v])))
+    for r in rng.integers(0, u.values.shape[0], 5):
+        cells = np.nonzero(np.any(u.cell_to_dof == r, axis=1))[0]
+        if cells.size == 0:
+            continue
+        sub = I.Mesh(3, mesh.n, mesh.coords, mesh.cells[cells])
+        f = I.Field(u.values, u.cell_to_dof[cells], 2, 3)
+        _, _, fref = oracle.adjoint("svk_energy", sub, 2, fields=[f], constants=w.constants)
+        np.testing.assert_allclose(gu[r], fref[0][r], rtol=1e-9, atol=1e-10 * np.max(np.abs(fref[0][r])))
