@@ -5,11 +5,9 @@
  * a mesh, the element tensor of a variational form by mapping the cell to a
  * reference simplex, evaluating basis functions and coefficient fields at
  * quadrature points and summing integrand * |det J| * weight. The paper's
- * per-cell contract (Fig. 1; Listing 1 `helmholtz(double A[3][3], double
- * **coords)`, Listing 2 `burgers(double A[12][12], double **coords,
- * double **w)`; Table 1 for the objects) takes a zeroed element matrix, the
- * element's coordinates and its coefficient fields. These entry points apply
- * that contract to whole meshes on one GPU.
+ * per-cell kernels (Fig. 1; Listings 1 and 2; Table 1 for the objects) take
+ * a zeroed element matrix, the element's coordinates and its coefficient
+ * fields. These entry points apply that contract to whole meshes on one GPU.
  *
  * Conventions shared by every entry point:
  *  - Reference cells: triangle (0,0),(1,0),(0,1); tetrahedron 0,e1,e2,e3.
@@ -73,7 +71,10 @@ typedef enum {
 
 typedef enum {
     COFFEE_FP64 = 0,   /* FP64 everywhere, FP64 output                                          */
-    COFFEE_FP32 = 1,   /* FP64 geometry, FP32 contraction, FP32 output                         */
+    COFFEE_FP32 = 1,   /* FP64 geometry (J, det J, K); FP32 contraction, FP32 output. The SVK
+                          energy and residual compute their point arithmetic (F, E, S, P) in
+                          FP32 from the FP64 geometry; the SVK Jacobian forms F, S and the
+                          tangent in FP64 and accumulates the element matrix in FP32.           */
     COFFEE_BF16X3 = 2  /* FP64 geometry; each contraction operand x split as x_hi = bf16(x),
                           x_lo = bf16(x - x_hi); hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32
                           accumulation; FP32 output                                             */
@@ -123,20 +124,30 @@ coffee_status coffee_assemble(int form, int cell, int degree, int quad_degree, i
                               int64_t ncells, const coffee_field* coeffs, int ncoeff,
                               const double* constants, int nconst, void* out, void* hip_stream);
 
-/* Reverse mode of the assembly (FP64). With S = sum_e lam_e^T A_e u_e
- * (bilinear forms), sum_e lam_e^T b_e (residual) or sum_e Pi_e (energy),
- * accumulates (+=) seed * dS/dcoords into grad_coords [nvert][d] and
- * seed * dS/dvalues into grad_coeff_values[i] (shaped like coeffs[i].values;
- * NULL entries or a NULL array skip). lam, u: device [ncells][N] FP64 (lam
- * unused for the energy, u unused for residual and energy). If cell_value is
- * not NULL it receives S_e per cell [ncells] FP64 (unscaled).
- * deterministic = 0: FP64 atomics; 1: per-cell gradients are written to
- * `workspace` and summed per vertex / dof in a fixed order (bitwise
- * reproducible). workspace: device buffer of at least
- * coffee_adjoint_workspace_size(...) bytes (may be NULL if deterministic = 0).
- * Not a paper passage: the adjoint serves PDE-constrained optimisation and
- * shape derivatives of the assembled forms.
- * Errors as coffee_assemble, plus COFFEE_E_BUFFER_TOO_SMALL. */
+/* Reverse mode of the assembly (FP64), the derivative of the per-cell kernel
+ * of section 2 (Fig. 1) with respect to its inputs; the paper itself has no
+ * reverse pass (it serves PDE-constrained optimisation and shape derivatives).
+ * S = sum_e lam_e^T A_e u_e for the bilinear forms (mass, Helmholtz,
+ * elasticity, Burgers), sum_e lam_e^T b_e for COFFEE_SVK_RESIDUAL, sum_e Pi_e
+ * for COFFEE_SVK_ENERGY. Accumulates (+=) seed * dS/dcoords into grad_coords
+ * [nvert][d] and seed * dS/dvalues into grad_coeff_values[i] (shaped like
+ * coeffs[i].values). A NULL grad_coords, a NULL grad_coeff_values array or a
+ * NULL entry skips that gradient (all NULL: only the values). lam, u: device
+ * [ncells][N] FP64, component-blocked like the element tensors (bilinear
+ * forms need both; the residual needs lam; the energy neither). If
+ * cell_value is not NULL it receives S_e per cell [ncells] FP64 (unscaled).
+ * deterministic = 0: the per-cell gradients are combined per wave in LDS and
+ *   scatter-added with FP64 atomics (sums are order-dependent in the last
+ *   bits); workspace may be NULL.
+ * deterministic = 1: the per-cell gradients are written to `workspace`, then
+ *   each vertex's and dof's contributions are summed in increasing cell order
+ *   (a stable sort of the cell-to-vertex / cell-to-dof entries by target):
+ *   the result is bitwise reproducible. workspace: device buffer, 256-byte
+ *   aligned, of at least coffee_adjoint_workspace_size(...) bytes.
+ * COFFEE_SVK_JACOBIAN has no reverse pass (COFFEE_E_UNSUPPORTED).
+ * Errors as coffee_assemble, plus COFFEE_E_BUFFER_TOO_SMALL (workspace),
+ * COFFEE_E_INVALID_ARG (deterministic not 0/1; NULL workspace with
+ * deterministic = 1; NULL lam or u where the form needs them). */
 coffee_status coffee_assemble_adjoint(int form, int cell, int degree, int quad_degree,
                                       const double* coords, int64_t nvert, const int32_t* cell_to_vertex,
                                       int64_t ncells, const coffee_field* coeffs, int ncoeff,
@@ -146,7 +157,11 @@ coffee_status coffee_assemble_adjoint(int form, int cell, int degree, int quad_d
                                       double* cell_value, int deterministic,
                                       void* workspace, int64_t workspace_bytes, void* hip_stream);
 
-/* Workspace bytes needed by the deterministic adjoint. */
+/* Workspace bytes of coffee_assemble_adjoint with deterministic = 1 for these
+ * sizes and fields (coeffs are read for their degree, component count and
+ * whether they have a dof map): per-cell gradients of the coordinates and of
+ * every field, plus the sort buffers. -1 for invalid arguments, or if the
+ * sort's size query fails (it needs a HIP device). */
 int64_t coffee_adjoint_workspace_size(int form, int cell, int degree, int64_t nvert, int64_t ncells,
                                       const coffee_field* coeffs, int ncoeff);
 
@@ -174,7 +189,9 @@ typedef struct {
  * extended to cells of different shape, degree and form in one launch).
  * Entry i of the batch is cell cell_of[i] of segment seg_of[i]; its element
  * tensor is written at out + out_offset[i] (elements, FP64 or FP32 by
- * precision; FP32 and FP64 supported). The entries are binned on the device
+ * precision; FP32 and FP64 supported). An entry whose seg_of is outside
+ * [0, nseg) or whose cell_of is outside its segment's mesh is skipped:
+ * nothing is read or written for it. The entries are binned on the device
  * (histograms, prefix sums, stable scatter of each entry's cell index and
  * output offset into per-bin ranges of the workspace), then one persistent kernel drains a
  * queue of bin tasks in segment order (put the costliest bins first). Output
@@ -193,7 +210,9 @@ coffee_status coffee_assemble_batch(int precision, const coffee_segment* segs, i
  * element tensors of segment 0 first, then segment 1, ..., each segment's
  * tensors contiguous and in increasing entry order, so that every tensor is
  * written as whole contiguous stores. out_offset (device, [nentries], int64)
- * is an output: out_offset[i] receives the element offset of entry i's tensor.
+ * is an output: out_offset[i] receives the element offset of entry i's tensor
+ * (-1 for a skipped entry, see coffee_assemble_batch; skipped entries take no
+ * space).
  * out must hold sum_i n_seg_of[i]^2 elements (16-byte aligned); the binning is
  * deterministic (the layout depends only on seg_of). Workspace, precision,
  * segments and errors as coffee_assemble_batch; the segments' variant is
@@ -206,8 +225,11 @@ coffee_status coffee_assemble_batch_packed(int precision, const coffee_segment* 
 /* Workspace bytes of coffee_assemble_batch and coffee_assemble_batch_packed. */
 int64_t coffee_batch_workspace_size(int nseg, int64_t nentries);
 
-/* Checks every cell: writes to *first_bad (device int64) the smallest cell
- * index with det J <= 0 or a non-finite coordinate, or -1 if none.
+/* Checks every cell for the geometry step of the per-cell kernel (section 2,
+ * Fig. 1: the Jacobian of the affine map and its determinant, which the
+ * kernels invert and use as |det J| without checking): writes to *first_bad
+ * (device int64) the smallest cell index with a vertex index outside
+ * [0, nvert), a non-finite coordinate or det J <= 0, or -1 if none.
  * Errors: COFFEE_E_INVALID_ARG. */
 coffee_status coffee_check_geometry(int cell, const double* coords, int64_t nvert,
                                     const int32_t* cell_to_vertex, int64_t ncells,

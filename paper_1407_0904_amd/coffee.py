@@ -232,11 +232,21 @@ def coffee_assemble(form, cell, degree: int, coords: torch.Tensor, cell_to_verte
     return out
 
 
+def coffee_adjoint_workspace_size(form, cell, degree: int, nvert: int, ncells: int, coeffs=()) -> int:
+    """Workspace bytes of the deterministic adjoint (coffee_adjoint_workspace_size)."""
+    fa = _fields(list(coeffs))
+    n = int(_lib.coffee_adjoint_workspace_size(FORMS[form], CELLS[cell], degree, nvert, ncells, fa, len(coeffs)))
+    if n < 0:
+        raise CoffeeError(1, "coffee_adjoint_workspace_size")
+    return n
+
+
 def coffee_assemble_adjoint(form, cell, degree: int, coords, cell_to_vertex, coeffs=(), constants=(),
                             lam=None, u=None, seed: float = 1.0, grad_coords=None, grad_coeffs=None,
                             cell_value=None, deterministic: bool = False, quad_degree: int = -1,
-                            workspace=None, stream=None):
-    """Accumulates seed * dS/d(coords, coefficient values); returns (grad_coords, grad_coeffs)."""
+                            workspace=None, grads: bool = True, stream=None):
+    """Accumulates seed * dS/d(coords, coefficient values); returns (grad_coords, grad_coeffs).
+    grads=False computes only the per-cell values (cell_value) and returns (None, [])."""
     c = CELLS[cell]
     _check_mesh(c, coords, cell_to_vertex)
     ncells = cell_to_vertex.shape[0]
@@ -246,9 +256,11 @@ def coffee_assemble_adjoint(form, cell, degree: int, coords, cell_to_vertex, coe
         _need(lam, "lam", torch.float64, shape=(ncells, N), allow_none=True)
         _need(u, "u", torch.float64, shape=(ncells, N), allow_none=True)
     _need(cell_value, "cell_value", torch.float64, numel=ncells, allow_none=True)
-    if grad_coords is None:
+    if not grads:
+        grad_coords, grad_coeffs = None, [None] * len(coeffs)
+    elif grad_coords is None:
         grad_coords = torch.zeros_like(coords)
-    _need(grad_coords, "grad_coords", torch.float64, shape=tuple(coords.shape))
+    _need(grad_coords, "grad_coords", torch.float64, shape=tuple(coords.shape), allow_none=not grads)
     if grad_coeffs is None:
         grad_coeffs = [torch.zeros_like(f.values) for f in coeffs]
     if len(grad_coeffs) != len(coeffs):
@@ -258,10 +270,13 @@ def coffee_assemble_adjoint(form, cell, degree: int, coords, cell_to_vertex, coe
     gptr = (C.c_void_p * max(1, len(coeffs)))(
         *[_dptr(g, torch.float64, "grad_coeffs", allow_none=True) for g in grad_coeffs])
     fa = _fields(list(coeffs))
-    if deterministic and workspace is None:
-        nbytes = _lib.coffee_adjoint_workspace_size(FORMS[form], c, degree, coords.shape[0], ncells, fa,
-                                                    len(coeffs))
-        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=coords.device)
+    if deterministic:
+        nbytes = coffee_adjoint_workspace_size(form, c, degree, coords.shape[0], ncells, coeffs)
+        if workspace is None:
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=coords.device)
+        _need(workspace, "workspace", torch.uint8)
+        if workspace.numel() < nbytes:
+            raise ValueError(f"workspace has {workspace.numel()} bytes, expected at least {nbytes}")
     cst = np.ascontiguousarray(constants, dtype=np.float64)
     st = _lib.coffee_assemble_adjoint(
         FORMS[form], c, degree, quad_degree,
@@ -269,11 +284,13 @@ def coffee_assemble_adjoint(form, cell, degree: int, coords, cell_to_vertex, coe
         _dptr(cell_to_vertex, torch.int32, "cell_to_vertex"), ncells, fa, len(coeffs),
         cst.ctypes.data if cst.size else None, cst.size,
         _dptr(lam, torch.float64, "lam", allow_none=True), _dptr(u, torch.float64, "u", allow_none=True),
-        float(seed), _dptr(grad_coords, torch.float64, "grad_coords"), gptr,
+        float(seed), _dptr(grad_coords, torch.float64, "grad_coords", allow_none=not grads), gptr,
         _dptr(cell_value, torch.float64, "cell_value", allow_none=True), int(bool(deterministic)),
         None if workspace is None else workspace.data_ptr(), 0 if workspace is None else workspace.numel(),
         _stream(stream))
     _check(st, "coffee_assemble_adjoint")
+    if not grads:
+        return None, []
     return grad_coords, grad_coeffs
 
 

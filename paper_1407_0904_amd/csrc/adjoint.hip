@@ -37,6 +37,11 @@ struct AdjArgs {
     double* grad_f0;         // shaped like f0 values, or NULL
     double* grad_f1;
     double* cell_value;      // [E] or NULL
+    // deterministic mode: per-cell contributions written here instead of
+    // scatter-added (scatter.hip sums them in a fixed order); NULL otherwise
+    double* det_x;           // [E][D+1][D]
+    double* det_f0;          // [E][nloc][ncomp of field 0]
+    double* det_f1;          // [E][nloc]
 };
 
 template <int FORM, int D, int FD>
@@ -137,10 +142,13 @@ __global__ __launch_bounds__(256) void k_adjoint_linear(AdjArgs A) {
          wbase += (int64_t)gridDim.x * blockDim.x) {
         const bool valid = wbase + lane < A.L.ncells;
         const int64_t cell = valid ? wbase + lane : A.L.ncells - 1;
-        combine_clear<D, TS>(ckx[wave], cvx[wave], lane);
-        if constexpr (Dirs::N0 > 0) combine_clear<W0, TS>(ck0[wave], cv0[wave], lane);
-        if constexpr (Dirs::N1 > 0) combine_clear<1, TS>(ck1[wave], cv1[wave], lane);
-        wave_sync();
+        const bool det = A.det_x != nullptr;  // same in every lane
+        if (!det) {
+            combine_clear<D, TS>(ckx[wave], cvx[wave], lane);
+            if constexpr (Dirs::N0 > 0) combine_clear<W0, TS>(ck0[wave], cv0[wave], lane);
+            if constexpr (Dirs::N1 > 0) combine_clear<1, TS>(ck1[wave], cv1[wave], lane);
+            wave_sync();
+        }
         CellIdx<FORM, D, FD> ix;
         CellRaw<FORM, D, FD> raw;
         load_idx<FORM, D, FD>(A.L, cell, ix);
@@ -191,43 +199,62 @@ __global__ __launch_bounds__(256) void k_adjoint_linear(AdjArgs A) {
                 }
                 vx[0][i] = sd * x0;
             }
+            if (det) {
 #pragma unroll
-            for (int v = 0; v <= D; ++v)
-                combine_add<D, TS>(ckx[wave], cvx[wave], (unsigned long long)ix.v[v], vx[v], A.grad_coords);
-            if constexpr (Dirs::N0 > 0) {
-                if (A.grad_f0) {
-                    constexpr int NF = Dirs::NF;
+                for (int v = 0; v <= D; ++v)
 #pragma unroll
-                    for (int r = 0; r < NF; ++r) {
-                        const int64_t key = A.L.f0.map ? (int64_t)ix.f0[r] : cell * NF + r;
-                        double v[W0];
+                    for (int i = 0; i < D; ++i) A.det_x[(cell * (D + 1) + v) * D + i] = vx[v][i];
+                if constexpr (Dirs::N0 > 0) {
 #pragma unroll
-                        for (int c = 0; c < W0; ++c) v[c] = sd * f0bar[r * W0 + c];
-                        combine_add<W0, TS>(ck0[wave], cv0[wave], (unsigned long long)key, v, A.grad_f0);
+                    for (int r = 0; r < Dirs::N0; ++r) A.det_f0[cell * Dirs::N0 + r] = sd * f0bar[r];
+                }
+                if constexpr (Dirs::N1 > 0) {
+#pragma unroll
+                    for (int r = 0; r < Dirs::N1; ++r) A.det_f1[cell * Dirs::N1 + r] = sd * f1bar[r];
+                }
+            } else {
+                if (A.grad_coords) {
+#pragma unroll
+                    for (int v = 0; v <= D; ++v)
+                        combine_add<D, TS>(ckx[wave], cvx[wave], (unsigned long long)ix.v[v], vx[v], A.grad_coords);
+                }
+                if constexpr (Dirs::N0 > 0) {
+                    if (A.grad_f0) {
+                        constexpr int NF = Dirs::NF;
+#pragma unroll
+                        for (int r = 0; r < NF; ++r) {
+                            const int64_t key = A.L.f0.map ? (int64_t)ix.f0[r] : cell * NF + r;
+                            double v[W0];
+#pragma unroll
+                            for (int c = 0; c < W0; ++c) v[c] = sd * f0bar[r * W0 + c];
+                            combine_add<W0, TS>(ck0[wave], cv0[wave], (unsigned long long)key, v, A.grad_f0);
+                        }
                     }
                 }
+                if constexpr (Dirs::N1 > 0) {
+                    if (A.grad_f1) {
+                        constexpr int NF = Dirs::NF;
+#pragma unroll
+                        for (int r = 0; r < NF; ++r) {
+                            const int64_t key = A.L.f1.map ? (int64_t)ix.f1[r] : cell * NF + r;
+                            const double v = sd * f1bar[r];
+                            combine_add<1, TS>(ck1[wave], cv1[wave], (unsigned long long)key, &v, A.grad_f1);
+                        }
+                    }
+                }
+            }
+        }
+        if (!det) {
+            wave_sync();
+            if (A.grad_coords) combine_flush<D, TS>(ckx[wave], cvx[wave], A.grad_coords, lane);
+            if constexpr (Dirs::N0 > 0) {
+                if (A.grad_f0) combine_flush<W0, TS>(ck0[wave], cv0[wave], A.grad_f0, lane);
             }
             if constexpr (Dirs::N1 > 0) {
-                if (A.grad_f1) {
-                    constexpr int NF = Dirs::NF;
-#pragma unroll
-                    for (int r = 0; r < NF; ++r) {
-                        const int64_t key = A.L.f1.map ? (int64_t)ix.f1[r] : cell * NF + r;
-                        const double v = sd * f1bar[r];
-                        combine_add<1, TS>(ck1[wave], cv1[wave], (unsigned long long)key, &v, A.grad_f1);
-                    }
-                }
+                if (A.grad_f1) combine_flush<1, TS>(ck1[wave], cv1[wave], A.grad_f1, lane);
             }
+            wave_sync();
         }
-        wave_sync();
-        combine_flush<D, TS>(ckx[wave], cvx[wave], A.grad_coords, lane);
-        if constexpr (Dirs::N0 > 0) {
-            if (A.grad_f0) combine_flush<W0, TS>(ck0[wave], cv0[wave], A.grad_f0, lane);
-        }
-        if constexpr (Dirs::N1 > 0) {
-            if (A.grad_f1) combine_flush<1, TS>(ck1[wave], cv1[wave], A.grad_f1, lane);
-        }
-        wave_sync();
     }
 }
 
@@ -267,10 +294,13 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
          base += (int64_t)gridDim.x * blockDim.x) {
         const bool valid = base + lane < A.L.ncells;
         const int64_t cell = valid ? base + lane : A.L.ncells - 1;
-        combine_clear<D, TS>(ckx[wave], cvx[wave], lane);
-        combine_clear<1, TS>(ckf[wave][0], cvf[wave][0], lane);
-        combine_clear<1, TS>(ckf[wave][1], cvf[wave][1], lane);
-        wave_sync();
+        const bool det = A.det_x != nullptr;  // same in every lane
+        if (!det) {
+            combine_clear<D, TS>(ckx[wave], cvx[wave], lane);
+            combine_clear<1, TS>(ckf[wave][0], cvf[wave][0], lane);
+            combine_clear<1, TS>(ckf[wave][1], cvf[wave][1], lane);
+            wave_sync();
+        }
         CellIdx<F_ELAST, D, FD> ix;
         CellRaw<F_ELAST, D, FD> raw;
         load_idx<F_ELAST, D, FD>(A.L, cell, ix);
@@ -363,12 +393,17 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
             }
             S += mu * mub + lm * lmb;
             if constexpr (FD > 0) {
-                if (A.grad_f0 && valid) {
+                if (det) {
+                    if (valid) {
+                        A.det_f0[cell * NF + r] = A.seed * mub;
+                        A.det_f1[cell * NF + r] = A.seed * lmb;
+                    }
+                } else if (A.grad_f0 && valid) {
                     const int64_t i0 = A.L.f0.map ? (int64_t)A.L.f0.map[cell * NF + r] : cell * NF + r;
                     const double x = A.seed * mub;
                     combine_add<1, TS>(ckf[wave][0], cvf[wave][0], (unsigned long long)i0, &x, A.grad_f0);
                 }
-                if (A.grad_f1 && valid) {
+                if (!det && A.grad_f1 && valid) {
                     const int64_t i1 = A.L.f1.map ? (int64_t)A.L.f1.map[cell * NF + r] : cell * NF + r;
                     const double x = A.seed * lmb;
                     combine_add<1, TS>(ckf[wave][1], cvf[wave][1], (unsigned long long)i1, &x, A.grad_f1);
@@ -402,15 +437,24 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_elast(AdjArgs A) {
                 }
                 vx[0][i] = sd * x0;
             }
+            if (det) {
 #pragma unroll
-            for (int v = 0; v <= D; ++v)
-                combine_add<D, TS>(ckx[wave], cvx[wave], (unsigned long long)ix.v[v], vx[v], A.grad_coords);
+                for (int v = 0; v <= D; ++v)
+#pragma unroll
+                    for (int i = 0; i < D; ++i) A.det_x[(cell * (D + 1) + v) * D + i] = vx[v][i];
+            } else if (A.grad_coords) {
+#pragma unroll
+                for (int v = 0; v <= D; ++v)
+                    combine_add<D, TS>(ckx[wave], cvx[wave], (unsigned long long)ix.v[v], vx[v], A.grad_coords);
+            }
         }
-        wave_sync();
-        combine_flush<D, TS>(ckx[wave], cvx[wave], A.grad_coords, lane);
-        if (A.grad_f0) combine_flush<1, TS>(ckf[wave][0], cvf[wave][0], A.grad_f0, lane);
-        if (A.grad_f1) combine_flush<1, TS>(ckf[wave][1], cvf[wave][1], A.grad_f1, lane);
-        wave_sync();
+        if (!det) {
+            wave_sync();
+            if (A.grad_coords) combine_flush<D, TS>(ckx[wave], cvx[wave], A.grad_coords, lane);
+            if (A.grad_f0) combine_flush<1, TS>(ckf[wave][0], cvf[wave][0], A.grad_f0, lane);
+            if (A.grad_f1) combine_flush<1, TS>(ckf[wave][1], cvf[wave][1], A.grad_f1, lane);
+            wave_sync();
+        }
     }
 }
 
@@ -494,12 +538,12 @@ coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, cons
                              const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, int ncoeff,
                              const double* constants, int nconst, const double* lam, const double* u,
                              double seed, double* grad_coords, double* const* grad_coeff_values,
-                             double* cell_value, void* hip_stream) {
+                             double* cell_value, const DetTarget* det, void* hip_stream) {
     const AdjEntry* e = nullptr;
     for (const AdjEntry& x : adj_registry())
         if (x.form == form && x.dim == cell && x.p == degree && x.fd == fd) e = &x;
     if (!e) return COFFEE_E_UNSUPPORTED;
-    if (ncells > 0 && (!lam || !u || !grad_coords)) return COFFEE_E_INVALID_ARG;
+    if (ncells > 0 && (!lam || !u)) return COFFEE_E_INVALID_ARG;
     if (ncells == 0) return COFFEE_OK;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return COFFEE_E_HIP;
@@ -528,6 +572,11 @@ coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, cons
     a.grad_f0 = (grad_coeff_values && ncoeff >= 1) ? grad_coeff_values[0] : nullptr;
     a.grad_f1 = (grad_coeff_values && ncoeff >= 2) ? grad_coeff_values[1] : nullptr;
     a.cell_value = cell_value;
+    if (det) {
+        a.det_x = det[0].local;
+        a.det_f0 = ncoeff >= 1 ? det[1].local : nullptr;
+        a.det_f1 = ncoeff >= 2 ? det[2].local : nullptr;
+    }
     const int64_t blocks = (ncells + 255) / 256;
     const int grid = (int)std::min<int64_t>(blocks, (int64_t)num_cu(dev) * 8);
     if (e->launch(a, (hipStream_t)hip_stream, grid) != hipSuccess) return COFFEE_E_HIP;

@@ -50,11 +50,16 @@ struct SvkArgs {
     double mu, lambda;
     const double* tab;   // W[nq] then dphi[D][nq][NS]
     void* out;
-    // reverse pass of the energy
+    // reverse passes (energy; residual against lam)
     double seed;
     double* grad_coords;
     double* grad_u;
     double* cell_value;
+    const double* lam;   // residual reverse pass: [E][D * NS] component-blocked
+    // deterministic mode: per-cell contributions written here instead of
+    // scatter-added (scatter.hip sums them in a fixed order); NULL otherwise
+    double* det_x;       // [E][D+1][D]
+    double* det_u;       // [E][NS][D]
 };
 
 // Reference-table read: through the scalar path when the address is the same
@@ -203,6 +208,76 @@ typedef unsigned int svk_u32x4 __attribute__((ext_vector_type(4)));
 template <int D, int P>
 constexpr int svk_tab_elems(int nq) { return nq + D * nq * nsc(D, P); }
 
+// The per-cell results of a reverse pass: the vertex-coordinate gradients vx
+// (seed already applied) and, if U, the displacement-dof gradients
+// f * g[c * NS + r] (component-blocked). Deterministic mode writes them to
+// the cell's slots of the workspace; otherwise they are scatter-added through
+// the wave's combining tables.
+template <int D, int NS, int TS, int TU, bool U, typename GT>
+__device__ inline void svk_scatter_cell(const SvkArgs& A, bool det, int64_t cell, const int (&vid)[D + 1],
+                                        const int (&uid)[NS], const double (&vx)[D + 1][D], const GT* g, double f,
+                                        unsigned long long* ckeys, double* cvals, unsigned long long* ukeys,
+                                        double* uvals) {
+    if (det) {
+#pragma unroll
+        for (int v = 0; v <= D; ++v)
+#pragma unroll
+            for (int i = 0; i < D; ++i) A.det_x[(cell * (D + 1) + v) * D + i] = vx[v][i];
+        if constexpr (U) {
+#pragma unroll
+            for (int r = 0; r < NS; ++r)
+#pragma unroll
+                for (int c = 0; c < D; ++c) A.det_u[(cell * NS + r) * D + c] = f * (double)g[c * NS + r];
+        }
+        return;
+    }
+    if (A.grad_coords) {
+#pragma unroll
+        for (int v = 0; v <= D; ++v)
+            combine_add<D, TS>(ckeys, cvals, (unsigned long long)vid[v], vx[v], A.grad_coords);
+    }
+    if constexpr (U) {
+#pragma unroll
+        for (int r = 0; r < NS; ++r) {
+            const unsigned long long key = A.u.map ? (unsigned long long)uid[r] : (unsigned long long)(cell * NS + r);
+            double v[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) v[c] = f * (double)g[c * NS + r];
+            combine_add<D, TU>(ukeys, uvals, key, v, A.grad_u);
+        }
+    }
+}
+
+// Vertex-coordinate gradients of a cell from Kbar = dS/dK (already scaled by
+// |det J|) and S (every term is linear in |det J|):
+//   Jbar = -K^T Kbar K^T + S K^T,  xbar_{j+1} = Jbar[:, j],  xbar_0 = -sum_j Jbar[:, j].
+template <int D>
+__device__ inline void svk_coord_bars(const double (&K)[D][D], const double (&Kbar)[D][D], double S, double sd,
+                                      double (&vx)[D + 1][D]) {
+    double Jbar[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = 0; b < D; ++b) s += K[a][i] * Kbar[a][b] * K[j][b];
+            Jbar[i][j] = -s + S * K[j][i];
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double x0 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            vx[j + 1][i] = sd * Jbar[i][j];
+            x0 -= Jbar[i][j];
+        }
+        vx[0][i] = sd * x0;
+    }
+}
+
 // MODE 0: energy, 1: residual, 2: reverse pass of the energy (coordinates),
 // 3: the reverse pass with the displacement gradient (the residual) too.
 template <int D, int P, int NQ, int MODE, typename OT>
@@ -229,7 +304,8 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
          base += (int64_t)gridDim.x * blockDim.x) {
         const bool valid = base + lane < A.ncells;
         const int64_t cell = valid ? base + lane : A.ncells - 1;
-        if constexpr (REV) {
+        const bool det = A.det_x != nullptr;  // same in every lane
+        if (REV && !det) {
             combine_clear<D, TS>(ckeys[wave], cvals[wave], lane);
             if constexpr (MODE == 3) combine_clear<D, TU>(ukeys[wave], uvals[wave], lane);
             wave_sync();
@@ -330,51 +406,211 @@ __global__ __launch_bounds__(256) void k_svk_vec(SvkArgs A) {
             for (int i = 0; i < D; ++i)
 #pragma unroll
                 for (int j = 0; j < D; ++j) Kbar[i][j] *= ad;
-            double Jbar[D][D];
+            const double sd = A.seed;
+            if (valid) {
+                double vx[D + 1][D];
+                svk_coord_bars<D>(g.K, Kbar, Pi, sd, vx);
+                svk_scatter_cell<D, NS, TS, TU, MODE == 3>(A, det, cell, vid, uid, vx, res, sd * ad, ckeys[wave],
+                                                           cvals[wave], ukeys[wave], uvals[wave]);
+            }
+            if (!det) {
+                wave_sync();
+                if (A.grad_coords) combine_flush<D, TS>(ckeys[wave], cvals[wave], A.grad_coords, lane);
+                if constexpr (MODE == 3) combine_flush<D, TU>(ukeys[wave], uvals[wave], A.grad_u, lane);
+                wave_sync();
+            }
+        }
+    }
+}
+
+// Reverse pass of the residual: S_e = lam_e^T b_e with b_(c,a) = sum_q w |det J|
+// P(F) : grad phi_a e_c, i.e. S_e = sum_q w |det J| P : L with L = Lam K the
+// physical gradient of the field lam_e (Lam[c][al] = sum_a lam_(c,a) dphi_a/dX_al).
+// Per point, with Pbar = w L and Lbar = w P (|det J| applied at the end):
+//   P = F S(F):  Fbar = Pbar S + F sym(Z),  M = F^T Pbar,  Z = lambda tr(M) I + 2 mu M
+//                (S symmetric; dS = lambda tr(dE) I + 2 mu dE, dE = (dF^T F + F^T dF)/2)
+//   F = I + U K: Ubar = Fbar K^T -> u-dof bars Ubar dphi_r;  Kbar += U^T Fbar
+//   L = Lam K:   Kbar += Lam^T Lbar
+// so the displacement gradient is (db/du)^T lam = A_e lam_e (the Jacobian is
+// symmetric). One thread per cell, FP64.
+template <int D, int P, int NQ>
+__global__ __launch_bounds__(256) void k_svk_res_adj(SvkArgs A) {
+    constexpr int NS = nsc(D, P), N = D * NS;
+    const double* W = A.tab;
+    const double* dphi = A.tab + NQ;
+    constexpr int TS = 256;
+    __shared__ unsigned long long ckeys[4][TS], ukeys[4][TS];
+    __shared__ double cvals[4][TS * D], uvals[4][TS * D];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double mu = A.mu, lm = A.lambda;
+    for (int64_t base = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) - lane; base < A.ncells;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const bool valid = base + lane < A.ncells;
+        const int64_t cell = valid ? base + lane : A.ncells - 1;
+        const bool det = A.det_x != nullptr;
+        if (!det) {
+            combine_clear<D, TS>(ckeys[wave], cvals[wave], lane);
+            combine_clear<D, TS>(ukeys[wave], uvals[wave], lane);
+            wave_sync();
+        }
+        Geom<D> g;
+        double uv[NS * D];
+        int vid[D + 1], uid[NS];
+        svk_load<D, NS>(A, cell, g, uv, vid, uid);
+        const auto& K = g.K;
+        const double* lam = A.lam + cell * N;
+        double val = 0.0, Kbar[D][D], gu[N];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Kbar[i][j] = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) gu[i] = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+            const double* dq = dphi + q * NS;
+            double U[D][D], Lm[D][D];  // reference gradients of u and of lam
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int al = 0; al < D; ++al) {
+                    double s = 0.0, t = 0.0;
+#pragma unroll
+                    for (int r = 0; r < NS; ++r) {
+                        const double dp = cload(dq + (size_t)al * NQ * NS + r);
+                        s += uv[r * D + i] * dp;
+                        t += lam[i * NS + r] * dp;
+                    }
+                    U[i][al] = s;
+                    Lm[i][al] = t;
+                }
+            double H[D][D], F[D][D], L[D][D];
 #pragma unroll
             for (int i = 0; i < D; ++i)
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
-                    double s = 0.0;
+                    double h = 0.0, l = 0.0;
 #pragma unroll
-                    for (int a = 0; a < D; ++a)
-#pragma unroll
-                        for (int b = 0; b < D; ++b) s += g.K[a][i] * Kbar[a][b] * g.K[j][b];
-                    Jbar[i][j] = -s + Pi * g.K[j][i];
+                    for (int a = 0; a < D; ++a) {
+                        h += U[i][a] * K[a][j];
+                        l += Lm[i][a] * K[a][j];
+                    }
+                    H[i][j] = h;
+                    F[i][j] = (i == j ? 1.0 : 0.0) + h;
+                    L[i][j] = l;
                 }
-            const double sd = A.seed;
-            if (valid) {
-                double vx[D + 1][D];
+            double E[D][D], trE = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    double t = H[i][j] + H[j][i];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) t += H[k][i] * H[k][j];
+                    E[i][j] = 0.5 * t;
+                }
+#pragma unroll
+            for (int i = 0; i < D; ++i) trE += E[i][i];
+            double S[D][D], Pm[D][D];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) S[i][j] = (i == j ? lm * trE : 0.0) + 2.0 * mu * E[i][j];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) t += F[i][k] * S[k][j];
+                    Pm[i][j] = t;
+                }
+            const double wq = cload(W + q);
+            double pl = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) pl += Pm[i][j] * L[i][j];
+            val += wq * pl;
+            // M = F^T Pbar with Pbar = w L; Z = lambda tr(M) I + 2 mu M
+            double M[D][D], trM = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) t += F[k][i] * L[k][j];
+                    M[i][j] = wq * t;
+                }
+#pragma unroll
+            for (int i = 0; i < D; ++i) trM += M[i][i];
+            // Fbar = Pbar S + F sym(Z), sym(Z) = lambda tr(M) I + mu (M + M^T)
+            double Fb[D][D];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    double t = 0.0, z = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        t += L[i][k] * S[k][j];
+                        z += F[i][k] * ((k == j ? lm * trM : 0.0) + mu * (M[k][j] + M[j][k]));
+                    }
+                    Fb[i][j] = wq * t + z;
+                }
+            // Kbar += U^T Fbar + Lam^T (w P); Ubar = Fbar K^T -> u-dof bars
+#pragma unroll
+            for (int al = 0; al < D; ++al)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) t += U[i][al] * Fb[i][j] + Lm[i][al] * wq * Pm[i][j];
+                    Kbar[al][j] += t;
+                }
+            double Ub[D][D];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int al = 0; al < D; ++al) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) t += Fb[i][j] * K[al][j];
+                    Ub[i][al] = t;
+                }
+#pragma unroll
+            for (int r = 0; r < NS; ++r) {
+                double dp[D];
+#pragma unroll
+                for (int al = 0; al < D; ++al) dp[al] = cload(dq + (size_t)al * NQ * NS + r);
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
-                    double x0 = 0.0;
+                    double t = 0.0;
 #pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        vx[j + 1][i] = sd * Jbar[i][j];
-                        x0 -= Jbar[i][j];
-                    }
-                    vx[0][i] = sd * x0;
-                }
-#pragma unroll
-                for (int v = 0; v <= D; ++v)
-                    combine_add<D, TS>(ckeys[wave], cvals[wave], (unsigned long long)vid[v], vx[v], A.grad_coords);
-                if constexpr (MODE == 3) {
-                    // seed * residual into grad_u
-                    const double f = sd * ad;
-#pragma unroll
-                    for (int r = 0; r < NS; ++r) {
-                        const unsigned long long key =
-                            A.u.map ? (unsigned long long)uid[r] : (unsigned long long)(cell * NS + r);
-                        double v[D];
-#pragma unroll
-                        for (int c = 0; c < D; ++c) v[c] = f * res[c * NS + r];
-                        combine_add<D, TU>(ukeys[wave], uvals[wave], key, v, A.grad_u);
-                    }
+                    for (int al = 0; al < D; ++al) t += Ub[i][al] * dp[al];
+                    gu[i * NS + r] += t;
                 }
             }
+        }
+        const double ad = g.adet;
+        const double Se = ad * val;
+        if (A.cell_value && valid) A.cell_value[cell] = Se;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Kbar[i][j] *= ad;
+        const double sd = A.seed;
+        if (valid) {
+            double vx[D + 1][D];
+            svk_coord_bars<D>(K, Kbar, Se, sd, vx);
+            svk_scatter_cell<D, NS, TS, TS, true>(A, det, cell, vid, uid, vx, gu, sd * ad, ckeys[wave], cvals[wave],
+                                                  ukeys[wave], uvals[wave]);
+        }
+        if (!det) {
             wave_sync();
-            combine_flush<D, TS>(ckeys[wave], cvals[wave], A.grad_coords, lane);
-            if constexpr (MODE == 3) combine_flush<D, TU>(ukeys[wave], uvals[wave], A.grad_u, lane);
+            if (A.grad_coords) combine_flush<D, TS>(ckeys[wave], cvals[wave], A.grad_coords, lane);
+            if (A.grad_u) combine_flush<D, TS>(ukeys[wave], uvals[wave], A.grad_u, lane);
             wave_sync();
         }
     }
@@ -667,8 +903,12 @@ hipError_t launch_svk(int form, int precision, const dev::SvkArgs& a, hipStream_
     const int64_t blocks = (a.ncells + 255) / 256;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)ncu * 8));
     if (reverse) {
-        if (a.grad_u) hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 3, double>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 2, double>), dim3(grid), dim3(256), 0, s, a);
+        if (form == COFFEE_SVK_RESIDUAL)
+            hipLaunchKernelGGL((dev::k_svk_res_adj<D, P, NQ>), dim3(grid), dim3(256), 0, s, a);
+        else if (a.grad_u || a.det_u)
+            hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 3, double>), dim3(grid), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((dev::k_svk_vec<D, P, NQ, 2, double>), dim3(grid), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     const bool f64 = precision == COFFEE_FP64;
@@ -742,11 +982,11 @@ coffee_status assemble_svk(int form, int cell, int degree, int q, int precision,
     return e == hipSuccess ? COFFEE_OK : COFFEE_E_HIP;
 }
 
-coffee_status adjoint_svk_energy(int cell, int degree, int q, const double* coords, const int32_t* c2v, int64_t ncells,
-                                 const coffee_field* coeffs, const double* constants, int nconst, double seed,
-                                 double* grad_coords, double* const* grad_coeff_values, double* cell_value,
-                                 void* hip_stream) {
-    if (ncells > 0 && !grad_coords) return COFFEE_E_INVALID_ARG;
+coffee_status adjoint_svk(int form, int cell, int degree, int q, const double* coords, const int32_t* c2v,
+                          int64_t ncells, const coffee_field* coeffs, const double* constants, int nconst,
+                          const double* lam, double seed, double* grad_coords, double* const* grad_coeff_values,
+                          double* cell_value, const DetTarget* det, void* hip_stream) {
+    if (form == COFFEE_SVK_RESIDUAL && ncells > 0 && !lam) return COFFEE_E_INVALID_ARG;
     if (ncells == 0) return COFFEE_OK;
     dev::SvkArgs a;
     const double* tab = nullptr;
@@ -757,11 +997,34 @@ coffee_status adjoint_svk_energy(int cell, int degree, int q, const double* coor
     a.grad_coords = grad_coords;
     a.grad_u = grad_coeff_values ? grad_coeff_values[0] : nullptr;
     a.cell_value = cell_value;
+    a.lam = lam;
+    if (det) {
+        a.det_x = det[0].local;
+        a.det_u = det[1].local;
+    }
     bool found = false;
-    hipError_t e = dispatch_svk(COFFEE_SVK_ENERGY, cell, degree, q, COFFEE_FP64, a, (hipStream_t)hip_stream,
-                                num_cu(dev), true, &found);
+    hipError_t e = dispatch_svk(form, cell, degree, q, COFFEE_FP64, a, (hipStream_t)hip_stream, num_cu(dev), true,
+                                &found);
     if (!found) return COFFEE_E_UNSUPPORTED;
     return e == hipSuccess ? COFFEE_OK : COFFEE_E_HIP;
+}
+
+// The gradient arrays of a reverse pass as deterministic-scatter targets:
+// vertex coordinates (entries: cells x vertices, keys cell_to_vertex), then
+// each coefficient field (entries: cells x local dofs, keys its dof map, or
+// one entry per value for a cell-major field).
+int adjoint_det_targets(int cell, int64_t nvert, const int32_t* c2v, int64_t ncells, const coffee_field* coeffs,
+                        int ncoeff, double* grad_coords, double* const* grad_coeff_values, DetTarget* t) {
+    const int d = cell;
+    t[0] = DetTarget{c2v, 1, ncells * (d + 1), d, nvert, nullptr, grad_coords};
+    for (int i = 0; i < ncoeff; ++i) {
+        const int64_t n = ncells * n_scalar(d, coeffs[i].degree);
+        const int32_t* keys = coeffs[i].cell_to_dof;
+        // the field's dof count is not passed: its keys are sorted over 31 bits
+        t[1 + i] = DetTarget{keys, keys ? 1 : 0, n, coeffs[i].ncomp, keys ? ((int64_t)1 << 31) : n, nullptr,
+                             grad_coeff_values ? grad_coeff_values[i] : nullptr};
+    }
+    return 1 + ncoeff;
 }
 
 }  // namespace coffee
@@ -780,17 +1043,37 @@ extern "C" coffee_status coffee_assemble_adjoint(int form, int cell, int degree,
                                        constants, nconst, &q, &fd);
     if (st != COFFEE_OK) return st;
     if (deterministic != 0 && deterministic != 1) return COFFEE_E_INVALID_ARG;
-    if (deterministic) return COFFEE_E_UNSUPPORTED;
-    (void)workspace;
-    (void)workspace_bytes;
-    if (form == COFFEE_SVK_ENERGY)
-        return adjoint_svk_energy(cell, degree, q, coords, c2v, ncells, coeffs, constants, nconst, seed, grad_coords,
-                                  grad_coeff_values, cell_value, hip_stream);
-    if (form >= COFFEE_SVK_ENERGY) return COFFEE_E_UNSUPPORTED;
-    return adjoint_linear(form, cell, degree, q, fd, coords, nvert, c2v, ncells, coeffs, ncoeff, constants, nconst,
-                          lam, u, seed, grad_coords, grad_coeff_values, cell_value, hip_stream);
+    if (form == COFFEE_SVK_JACOBIAN) return COFFEE_E_UNSUPPORTED;
+    if (form < COFFEE_SVK_ENERGY && ncells > 0 && (!lam || !u)) return COFFEE_E_INVALID_ARG;
+    for (int i = 0; i < ncoeff; ++i)
+        if (coeffs[i].ncomp > 3) return COFFEE_E_UNSUPPORTED;
+    DetTarget det[3];
+    int ndet = 0;
+    if (deterministic) {
+        ndet = adjoint_det_targets(cell, nvert, c2v, ncells, coeffs, ncoeff, grad_coords, grad_coeff_values, det);
+        st = det_carve(workspace, workspace_bytes, det, ndet);
+        if (st != COFFEE_OK) return st;
+    }
+    if (form >= COFFEE_SVK_ENERGY)
+        st = adjoint_svk(form, cell, degree, q, coords, c2v, ncells, coeffs, constants, nconst, lam, seed,
+                         grad_coords, grad_coeff_values, cell_value, deterministic ? det : nullptr, hip_stream);
+    else
+        st = adjoint_linear(form, cell, degree, q, fd, coords, nvert, c2v, ncells, coeffs, ncoeff, constants, nconst,
+                            lam, u, seed, grad_coords, grad_coeff_values, cell_value, deterministic ? det : nullptr,
+                            hip_stream);
+    if (st != COFFEE_OK || !deterministic || ncells == 0) return st;
+    return det_scatter(det, ndet, workspace, (hipStream_t)hip_stream);
 }
 
-extern "C" int64_t coffee_adjoint_workspace_size(int, int, int, int64_t, int64_t, const coffee_field*, int) {
-    return 0;
+extern "C" int64_t coffee_adjoint_workspace_size(int form, int cell, int degree, int64_t nvert, int64_t ncells,
+                                                 const coffee_field* coeffs, int ncoeff) {
+    using namespace coffee;
+    if (form < COFFEE_MASS || form > COFFEE_SVK_RESIDUAL) return -1;
+    if ((cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) || degree < 1 || degree > kMaxP) return -1;
+    if (nvert < 0 || ncells < 0 || ncoeff < 0 || ncoeff > 2 || (ncoeff > 0 && !coeffs)) return -1;
+    for (int i = 0; i < ncoeff; ++i)
+        if (coeffs[i].degree < 1 || coeffs[i].degree > kMaxP || coeffs[i].ncomp < 1 || coeffs[i].ncomp > 3) return -1;
+    DetTarget det[3];
+    const int ndet = adjoint_det_targets(cell, nvert, nullptr, ncells, coeffs, ncoeff, nullptr, nullptr, det);
+    return det_workspace_bytes(det, ndet);
 }

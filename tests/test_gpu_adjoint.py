@@ -142,6 +142,118 @@ def test_autograd_bilinear_action(cf):
     S = bilinear_action("elasticity", 3, 2, coords, c2v, fields=dfs, lam=lam, u=u)
     (2.0 * S).backward()
     S0, gc, gf, _ = _gpu_adjoint(cf, "elasticity", w.mesh, 2, w.fields, [], w.lam, w.u)
-    assert abs(float(S) - S0) < 1e-12 * abs(S0)
+    assert abs(float(S.detach()) - S0) < 1e-12 * abs(S0)
     np.testing.assert_allclose(coords.grad.cpu().numpy(), 2 * gc, rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(dfs[0].values.grad.cpu().numpy(), 2 * gf[0], rtol=1e-12, atol=1e-14)
+
+
+def _det_case(form, d, p, rng, cellmajor=False):
+    """A small mesh with the form's coefficient fields (mapped, or cell-major)."""
+    mesh = I.make_mesh(d, 6 if d == 2 else 3, 0.15, rng)
+    if form == "elasticity":
+        fields = [I.Field(rng.uniform(1, 10, (mesh.nvert, 1)), mesh.cells, 1, 1),
+                  I.Field(rng.uniform(1, 10, (mesh.nvert, 1)), mesh.cells, 1, 1)]
+    elif form == "burgers":
+        c2d, nd = (mesh.cells, mesh.nvert) if p == 1 else I.p2_dofmap(mesh.cells, mesh.n, d)
+        fields = [I.Field(rng.uniform(-1, 1, (nd, d)), c2d, p, d)]
+    else:
+        c2d, nd = (mesh.cells, mesh.nvert) if p == 1 else I.p2_dofmap(mesh.cells, mesh.n, d)
+        fields = [I.Field(rng.uniform(0.5, 1.5, (nd, 1)), c2d, p, 1)]
+    if cellmajor:
+        fields = [I.Field(np.ascontiguousarray(f.values[f.cell_to_dof]), None, f.degree, f.ncomp) for f in fields]
+    return mesh, fields
+
+
+@pytest.mark.parametrize("form,d,p,cellmajor", [("elasticity", 3, 2, False), ("helmholtz", 3, 2, False),
+                                                ("mass", 3, 2, True), ("burgers", 3, 2, False),
+                                                ("burgers", 2, 1, True)])
+def test_deterministic_adjoint(cf, oracle, form, d, p, cellmajor):
+    """deterministic=1: two runs give the same bits; the result matches the
+    atomic scatter to rounding and the oracle's complex-step gradient."""
+    import torch
+    from gpu_util import to_dev
+    rng = np.random.default_rng(31 + p)
+    mesh, fields = _det_case(form, d, p, rng, cellmajor)
+    cst = [0.6, 1.4] if form == "burgers" else []
+    N = oracle.tensor_dim(form, d, p)
+    lam = rng.standard_normal((mesh.ncells, N))
+    u = rng.standard_normal((mesh.ncells, N))
+    S_ref, gc_ref, gf_ref = oracle.adjoint(form, mesh, p, fields=fields, constants=cst, lam=lam, u=u)
+    coords, c2v, dfs = to_dev(mesh, fields)
+    lam_d = torch.as_tensor(lam, device=coords.device)
+    u_d = torch.as_tensor(u, device=coords.device)
+    nbytes = cf.coffee_adjoint_workspace_size(form, d, p, mesh.nvert, mesh.ncells, dfs)
+    assert nbytes > 0
+    runs = []
+    for det in (True, True, False):
+        gc, gf = cf.coffee_assemble_adjoint(form, d, p, coords, c2v, coeffs=dfs, constants=cst, lam=lam_d, u=u_d,
+                                            deterministic=det)
+        torch.cuda.synchronize()
+        runs.append((gc.cpu().numpy(), [g.cpu().numpy() for g in gf]))
+    (a, af), (b, bf), (c, cfl) = runs
+    assert np.array_equal(a, b) and all(np.array_equal(x, y) for x, y in zip(af, bf))
+    assert rel(a, c) < 1e-13 and all(rel(x, y) < 1e-13 for x, y in zip(af, cfl))
+    assert rel(a, gc_ref) < 1e-10 and all(rel(x, y) < 1e-10 for x, y in zip(af, gf_ref))
+
+
+def test_deterministic_adjoint_full_size_elasticity(cf):
+    """The 663,552-cell elasticity adjoint in deterministic mode: bitwise
+    repeatable, and equal to the atomic scatter to rounding."""
+    import torch
+    from gpu_util import to_dev
+    w = I.workload("elasticity_p2_tet")
+    coords, c2v, dfs = to_dev(w.mesh, w.fields)
+    lam = torch.as_tensor(w.lam, device=coords.device)
+    u = torch.as_tensor(w.u, device=coords.device)
+    ws = torch.empty(cf.coffee_adjoint_workspace_size("elasticity", 3, 2, w.mesh.nvert, w.mesh.ncells, dfs),
+                     dtype=torch.uint8, device=coords.device)
+    out = []
+    for det in (True, True, False):
+        gc, gf = cf.coffee_assemble_adjoint("elasticity", 3, 2, coords, c2v, coeffs=dfs, lam=lam, u=u,
+                                            deterministic=det, workspace=ws if det else None)
+        torch.cuda.synchronize()
+        out.append([gc] + gf)
+    for x, y in zip(out[0], out[1]):
+        assert torch.equal(x, y)
+    for x, z in zip(out[0], out[2]):
+        assert float((x - z).abs().max()) <= 1e-12 * float(z.abs().max())
+
+
+def test_adjoint_workspace_checks(cf):
+    import torch
+    from gpu_util import to_dev
+    rng = np.random.default_rng(2)
+    mesh, fields = _det_case("helmholtz", 3, 2, rng)
+    coords, c2v, dfs = to_dev(mesh, fields)
+    N = 10
+    lam = torch.zeros((mesh.ncells, N), dtype=torch.float64, device=coords.device)
+    nbytes = cf.coffee_adjoint_workspace_size("helmholtz", 3, 2, mesh.nvert, mesh.ncells, dfs)
+    with pytest.raises(ValueError, match="workspace has"):
+        cf.coffee_assemble_adjoint("helmholtz", 3, 2, coords, c2v, coeffs=dfs, lam=lam, u=lam, deterministic=True,
+                                   workspace=torch.empty(nbytes - 1, dtype=torch.uint8, device=coords.device))
+    # the SVK Jacobian has no reverse pass
+    ud = cf.DeviceField(torch.zeros((mesh.nvert, 3), dtype=torch.float64, device=coords.device), c2v, 1, 3)
+    with pytest.raises(cf.CoffeeError) as ei:
+        cf.coffee_assemble_adjoint("svk_jacobian", 3, 1, coords, c2v, coeffs=[ud], lam=torch.zeros(
+            (mesh.ncells, 12), dtype=torch.float64, device=coords.device), u=torch.zeros(
+            (mesh.ncells, 12), dtype=torch.float64, device=coords.device))
+    assert ei.value.code == 2
+
+
+def test_value_only_reverse_pass(cf):
+    """grads=False computes the per-cell values alone, equal to those of the
+    full reverse pass."""
+    import torch
+    from gpu_util import to_dev
+    w = I.workload("elasticity_p2_tet", n=3)
+    coords, c2v, dfs = to_dev(w.mesh, w.fields)
+    lam = torch.as_tensor(w.lam, device=coords.device)
+    u = torch.as_tensor(w.u, device=coords.device)
+    cv0 = torch.empty(w.mesh.ncells, dtype=torch.float64, device=coords.device)
+    cv1 = torch.empty_like(cv0)
+    cf.coffee_assemble_adjoint("elasticity", 3, 2, coords, c2v, coeffs=dfs, lam=lam, u=u, cell_value=cv0)
+    gc, gf = cf.coffee_assemble_adjoint("elasticity", 3, 2, coords, c2v, coeffs=dfs, lam=lam, u=u, cell_value=cv1,
+                                        grads=False)
+    torch.cuda.synchronize()
+    assert gc is None and gf == []
+    assert torch.equal(cv0, cv1)

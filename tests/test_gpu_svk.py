@@ -156,3 +156,103 @@ def test_svk_energy_adjoint_full_size_sampled(cf, oracle):
         f = I.Field(u.values, u.cell_to_dof[cells], 2, 3)
         _, _, fref = oracle.adjoint("svk_energy", sub, 2, fields=[f], constants=w.constants)
         np.testing.assert_allclose(gu[r], fref[0][r], rtol=1e-9, atol=1e-10 * np.max(np.abs(fref[0][r])))
+
+
+@pytest.mark.parametrize("d,p", [(3, 1), (3, 2), (2, 2)])
+@pytest.mark.parametrize("det", [False, True])
+def test_svk_residual_adjoint(cf, oracle, d, p, det):
+    """Reverse pass of S = sum_e lam_e^T b_e against the oracle's complex-step
+    gradient; the displacement gradient also equals sum_e A_e lam_e with A_e
+    the GPU Jacobian (the residual's derivative), scattered to the dofs."""
+    import torch
+    from gpu_util import to_dev
+    rng = np.random.default_rng(80 + 10 * d + p)
+    mesh = I.make_mesh(d, 6 if d == 2 else 3, 0.1, rng)
+    u = _disp(mesh, p, rng)
+    cst = [1.2, 0.8]
+    N = oracle.tensor_dim("svk_residual", d, p)
+    lam = rng.standard_normal((mesh.ncells, N))
+    S_ref, gc_ref, gu_ref = oracle.adjoint("svk_residual", mesh, p, fields=[u], constants=cst, lam=lam)
+    coords, c2v, dfs = to_dev(mesh, [u])
+    lam_d = torch.as_tensor(lam, device=coords.device)
+    cv = torch.empty(mesh.ncells, dtype=torch.float64, device=coords.device)
+    gc, gu = cf.coffee_assemble_adjoint("svk_residual", d, p, coords, c2v, coeffs=dfs, constants=cst, lam=lam_d,
+                                        cell_value=cv, deterministic=det)
+    A = cf.coffee_assemble("svk_jacobian", d, p, coords, c2v, coeffs=dfs, constants=cst)
+    torch.cuda.synchronize()
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    S = float(cv.sum())
+    assert abs(S - S_ref) < 1e-11 * abs(S_ref)
+    assert rel(gc.cpu().numpy(), gc_ref) < 1e-10
+    assert rel(gu[0].cpu().numpy(), gu_ref[0]) < 1e-10
+    ns = I.n_scalar_dofs(d, p)
+    Al = torch.bmm(A, lam_d.unsqueeze(2)).reshape(mesh.ncells, d, ns).permute(0, 2, 1).reshape(-1, d)
+    scat = torch.zeros_like(dfs[0].values).index_add_(0, dfs[0].cell_to_dof.reshape(-1).long(), Al)
+    assert rel(gu[0].cpu().numpy(), scat.cpu().numpy()) < 1e-12
+
+
+def test_svk_energy_deterministic(cf):
+    """Energy reverse pass in deterministic mode on the full 196,608-cell P2
+    workload: bitwise repeatable, equal to the atomic scatter to rounding."""
+    import torch
+    from gpu_util import to_dev
+    w = I.workload("svk_p2_tet")
+    coords, c2v, dfs = to_dev(w.mesh, w.fields)
+    res = []
+    for det in (True, True, False):
+        gc, gu = cf.coffee_assemble_adjoint("svk_energy", 3, 2, coords, c2v, coeffs=dfs, constants=w.constants,
+                                            deterministic=det)
+        torch.cuda.synchronize()
+        res.append((gc, gu[0]))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    for k in range(2):
+        assert float((res[0][k] - res[2][k]).abs().max()) <= 1e-12 * float(res[2][k].abs().max())
+
+
+def test_autograd_energy_and_residual_action(cf):
+    """EnergyFn: gradients of Pi through torch.autograd equal the reverse pass,
+    dPi/du matches central differences of the GPU energy, and without
+    requires_grad the forward value is the same. ResidualActionFn likewise."""
+    import torch
+    from gpu_util import to_dev
+    from paper_1407_0904_amd.autograd import svk_energy, svk_residual_action
+    rng = np.random.default_rng(4)
+    mesh = I.make_mesh(3, 3, 0.1, rng)
+    u = _disp(mesh, 2, rng)
+    cst = [1.0, 1.0]
+    coords, c2v, dfs = to_dev(mesh, [u])
+    Pi0 = svk_energy(3, 2, coords, c2v, dfs[0], constants=cst)
+    coords.requires_grad_(True)
+    dfs[0].values.requires_grad_(True)
+    Pi = svk_energy(3, 2, coords, c2v, dfs[0], constants=cst)
+    Pi.backward()
+    gc, gu = cf.coffee_assemble_adjoint("svk_energy", 3, 2, coords.detach(), c2v,
+                                        coeffs=[cf.DeviceField(dfs[0].values.detach(), dfs[0].cell_to_dof, 2, 3)],
+                                        constants=cst)
+    torch.cuda.synchronize()
+    assert abs(float(Pi0) - float(Pi.detach())) <= 1e-14 * abs(float(Pi0))
+    assert torch.allclose(coords.grad, gc, rtol=1e-13, atol=1e-16)
+    assert torch.allclose(dfs[0].values.grad, gu[0], rtol=1e-13, atol=1e-16)
+
+    def energy_at(vals):
+        f = cf.DeviceField(vals, dfs[0].cell_to_dof, 2, 3)
+        return float(cf.coffee_assemble("svk_energy", 3, 2, coords.detach(), c2v, coeffs=[f], constants=cst).sum())
+
+    h = 1e-6
+    for (r, c) in ((5, 0), (40, 2)):
+        vp = dfs[0].values.detach().clone(); vp[r, c] += h
+        vm = dfs[0].values.detach().clone(); vm[r, c] -= h
+        fd = (energy_at(vp) - energy_at(vm)) / (2 * h)
+        g = float(dfs[0].values.grad[r, c])
+        assert abs(fd - g) <= 1e-6 * max(abs(fd), 1e-8)
+    lam = torch.as_tensor(rng.standard_normal((mesh.ncells, 30)), device=coords.device)
+    coords.grad = None
+    dfs[0].values.grad = None
+    S = svk_residual_action(3, 2, coords, c2v, dfs[0], lam, constants=cst)
+    S.backward()
+    gc2, gu2 = cf.coffee_assemble_adjoint("svk_residual", 3, 2, coords.detach(), c2v,
+                                          coeffs=[cf.DeviceField(dfs[0].values.detach(), dfs[0].cell_to_dof, 2, 3)],
+                                          constants=cst, lam=lam)
+    torch.cuda.synchronize()
+    assert torch.allclose(coords.grad, gc2, rtol=1e-13, atol=1e-16)
+    assert torch.allclose(dfs[0].values.grad, gu2[0], rtol=1e-13, atol=1e-16)
