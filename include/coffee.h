@@ -225,6 +225,31 @@ coffee_status coffee_assemble_batch_packed(int precision, const coffee_segment* 
 /* Workspace bytes of coffee_assemble_batch and coffee_assemble_batch_packed. */
 int64_t coffee_batch_workspace_size(int nseg, int64_t nentries);
 
+/* Largest batch of coffee_assemble_batch_packed_noalloc. */
+#define COFFEE_NOALLOC_MAX_ENTRIES 4194304
+
+/* coffee_assemble_batch_packed for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, bit for bit, with no
+ * workspace argument. Its scratch memory (binning counters, per-bin entry
+ * lists, the task queue: 48.3 MiB) is a static device array of the library,
+ * and its reference tables live in a second static device array of 1 MiB;
+ * each GPU the library runs on holds its own copy of both until the process
+ * ends. The call allocates nothing: the first call on a device looks up the
+ * arrays' addresses, and the first call that uses a bin type copies that
+ * type's tables into the table array with a synchronous hipMemcpy (make such
+ * a call once before capturing a graph). Every call on one GPU shares its
+ * scratch array, and the binning kernels rewrite all of it that a call reads
+ * (no clearing needed), so calls that overlap in time on one GPU (different
+ * streams, or host threads) race and must be serialised by the caller.
+ * Errors: as coffee_assemble_batch_packed, plus COFFEE_E_BUFFER_TOO_SMALL for
+ * nentries > COFFEE_NOALLOC_MAX_ENTRIES and COFFEE_E_NOMEM if the table array
+ * is full (it holds every bin type's tables in both precisions). */
+coffee_status coffee_assemble_batch_packed_noalloc(int precision, const coffee_segment* segs, int nseg,
+                                                   const int32_t* seg_of, const int64_t* cell_of,
+                                                   int64_t nentries, void* out, int64_t* out_offset,
+                                                   void* hip_stream);
+
 /* Checks every cell for the geometry step of the per-cell kernel (section 2,
  * Fig. 1: the Jacobian of the affine map and its determinant, which the
  * kernels invert and use as |det J| without checking): writes to *first_bad

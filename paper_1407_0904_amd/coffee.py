@@ -66,6 +66,8 @@ def _load():
     L.coffee_assemble_batch.restype = i32
     L.coffee_assemble_batch_packed.argtypes = [i32, vp, i32, vp, vp, i64, vp, vp, vp, i64, vp]
     L.coffee_assemble_batch_packed.restype = i32
+    L.coffee_assemble_batch_packed_noalloc.argtypes = [i32, vp, i32, vp, vp, i64, vp, vp, vp]
+    L.coffee_assemble_batch_packed_noalloc.restype = i32
     L.coffee_batch_workspace_size.argtypes = [i32, i64]
     L.coffee_batch_workspace_size.restype = i64
     L.coffee_load_tuning.argtypes = [C.c_char_p]
@@ -391,6 +393,34 @@ def coffee_assemble_batch_packed(segments, seg_of: torch.Tensor, cell_of: torch.
                                            _dptr(out_offset, torch.int64, "out_offset"),
                                            workspace.data_ptr(), workspace.numel(), _stream(stream))
     _check(st, "coffee_assemble_batch_packed")
+    return out, out_offset
+
+
+NOALLOC_MAX_ENTRIES = 4194304  # COFFEE_NOALLOC_MAX_ENTRIES
+
+
+def coffee_assemble_batch_packed_noalloc(segments, seg_of: torch.Tensor, cell_of: torch.Tensor, out: torch.Tensor,
+                                         out_offset: torch.Tensor, precision: str = "fp32", stream=None):
+    """coffee_assemble_batch_packed without a workspace: the library's static
+    device scratch array (at most NOALLOC_MAX_ENTRIES entries). The caller
+    passes the outputs; nothing is allocated."""
+    odt = torch.float64 if precision == "fp64" else torch.float32
+    n = seg_of.shape[0]
+    for i, sg in enumerate(segments):
+        d = CELLS[sg.cell]
+        _check_mesh(d, sg.coords, sg.cell_to_vertex, where=f"segments[{i}].")
+        _check_fields([sg.coeff], d, sg.cell_to_vertex.shape[0], where=f"segments[{i}].coeff")
+    _need(seg_of, "seg_of", torch.int32, shape=(n,))
+    _need(cell_of, "cell_of", torch.int64, shape=(n,))
+    _need(out_offset, "out_offset", torch.int64, shape=(n,))
+    _need(out, "out", odt)
+    segs, _keep = _segments(segments)
+    st = _lib.coffee_assemble_batch_packed_noalloc(PRECISIONS[precision], segs, len(segments),
+                                                   _dptr(seg_of, torch.int32, "seg_of"),
+                                                   _dptr(cell_of, torch.int64, "cell_of"), n,
+                                                   _dptr(out, odt, "out"),
+                                                   _dptr(out_offset, torch.int64, "out_offset"), _stream(stream))
+    _check(st, "coffee_assemble_batch_packed_noalloc")
     return out, out_offset
 
 

@@ -500,6 +500,15 @@ static const std::vector<AdjEntry>& adj_registry() {
 static std::mutex g_adj_mu;
 static std::map<std::tuple<int, int, int, int, int, int>, void*> g_adj_tables;  // (dev, form, dim, p, q, fd)
 
+// FP64 reference tensors [KR][NS * NS] (unpacked), host values.
+bool r64_table(int form, int dim, int p, int q, int fd, std::vector<double>& h) {
+    RefTensor R;
+    if (!build_reference(form, dim, p, q, fd, R)) return false;
+    h.resize(R.R.size());
+    for (size_t i = 0; i < h.size(); ++i) h[i] = (double)R.R[i];
+    return true;
+}
+
 // FP64 reference tensors [KR][NS * NS] (unpacked), built and uploaded on first
 // use; shared by the adjoint kernels and the degree-1 FMA kernels.
 coffee_status reference_table_f64(int dev, int form, int dim, int p, int q, int fd, const double** out) {
@@ -510,10 +519,8 @@ coffee_status reference_table_f64(int dev, int form, int dim, int p, int q, int 
         *out = (const double*)it->second;
         return COFFEE_OK;
     }
-    RefTensor R;
-    if (!build_reference(form, dim, p, q, fd, R)) return COFFEE_E_INVALID_ARG;
-    std::vector<double> h(R.R.size());
-    for (size_t i = 0; i < h.size(); ++i) h[i] = (double)R.R[i];
+    std::vector<double> h;
+    if (!r64_table(form, dim, p, q, fd, h)) return COFFEE_E_INVALID_ARG;
     void* d = nullptr;
     if (hipMalloc(&d, h.size() * sizeof(double)) != hipSuccess) return COFFEE_E_NOMEM;
     if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {

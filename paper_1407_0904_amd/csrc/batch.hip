@@ -25,6 +25,9 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -683,13 +686,86 @@ static int batch_type(int form, int cell, int degree) {
     return -1;
 }
 
+// ---------------------------------------------------------------- allocation-free variant
+//
+// coffee_assemble_batch_packed_noalloc takes its workspace from `scratch`, a
+// file-scope device array, and its reference tables from `table_pool`, a
+// second one, instead of caller memory and hipMalloc. In host code these
+// names are stand-ins, not device addresses: their addresses on the current
+// device come from hipGetSymbolAddress (each device holds its own copies) and
+// are the only form in which host code uses them.
+
+constexpr int64_t kScratchMaxEntries = COFFEE_NOALLOC_MAX_ENTRIES;
+constexpr int64_t kScratchBytes = kWsHeader + kWsArgs + kWsSlices + kScratchMaxEntries * 12;
+constexpr int64_t kTablePoolBytes = 1 << 20;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+__device__ __align__(256) unsigned char table_pool[kTablePoolBytes];
+
+struct NoallocDev {
+    unsigned char* scratch = nullptr;  // device address of `scratch`
+    unsigned char* pool = nullptr;     // device address of `table_pool`
+    int64_t used = 0;                  // bytes of the pool in use
+    std::map<std::tuple<int, int, int, int, int, int>, const void*> tabs;  // (kind, form, cell, degree, q, prec)
+};
+
+static std::mutex g_noalloc_mu;
+static std::map<int, NoallocDev> g_noalloc;
+
+// Set-up once per device (with that device current): the arrays' addresses.
+static coffee_status noalloc_device(int dev, NoallocDev** out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    NoallocDev& d = g_noalloc[dev];
+    if (!d.scratch) {
+        void* ps = nullptr;
+        void* pt = nullptr;
+        if (hipGetSymbolAddress(&ps, HIP_SYMBOL(scratch)) != hipSuccess || !ps) return COFFEE_E_HIP;
+        if (hipGetSymbolAddress(&pt, HIP_SYMBOL(table_pool)) != hipSuccess || !pt) return COFFEE_E_HIP;
+        d.scratch = static_cast<unsigned char*>(ps);
+        d.pool = static_cast<unsigned char*>(pt);
+    }
+    *out = &d;
+    return COFFEE_OK;
+}
+
+// A reference table in the pool, copied there on first use (a synchronous
+// host-to-device copy into the pool; no allocation).
+static coffee_status noalloc_table(NoallocDev& d, int kind, int form, int cell, int degree, int q, int prec,
+                                   const void** out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    const auto key = std::make_tuple(kind, form, cell, degree, q, prec);
+    auto it = d.tabs.find(key);
+    if (it != d.tabs.end()) {
+        *out = it->second;
+        return COFFEE_OK;
+    }
+    std::vector<char> bytes;
+    if (kind == 0) {
+        if (!rtable_bytes(form, cell, degree, q, 1, prec, bytes)) return COFFEE_E_INVALID_ARG;
+    } else {
+        std::vector<double> h;
+        if (!r64_table(form, cell, degree, q, 1, h)) return COFFEE_E_INVALID_ARG;
+        bytes.resize(h.size() * sizeof(double));
+        std::memcpy(bytes.data(), h.data(), bytes.size());
+    }
+    const int64_t n = ((int64_t)bytes.size() + 255) / 256 * 256;
+    if (d.used + n > kTablePoolBytes) return COFFEE_E_NOMEM;
+    unsigned char* dst = d.pool + d.used;
+    if (hipMemcpy(dst, bytes.data(), bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return COFFEE_E_HIP;
+    d.used += n;
+    d.tabs[key] = dst;
+    *out = dst;
+    return COFFEE_OK;
+}
+
 // packed = 0: tensors at the caller's out_offset (input); packed = 1: the
 // library lays the bins out contiguously in segment order (entries of a bin in
-// input order) and writes each entry's offset to out_offset_w.
+// input order) and writes each entry's offset to out_offset_w. na != NULL:
+// reference tables from the allocation-free pool.
 static coffee_status assemble_batch(int precision, const coffee_segment* segs, int nseg, const int32_t* seg_of,
                                     const int64_t* cell_of, const int64_t* out_offset, int64_t* out_offset_w,
                                     int packed, int64_t nentries, void* out, void* workspace,
-                                    int64_t workspace_bytes, void* hip_stream) {
+                                    int64_t workspace_bytes, void* hip_stream, NoallocDev* na = nullptr) {
     if (precision != COFFEE_FP64 && precision != COFFEE_FP32) return COFFEE_E_UNSUPPORTED;
     if (!segs || nseg < 1 || nseg > dev::kMaxBins || nentries < 0) return COFFEE_E_INVALID_ARG;
     if (nentries > INT32_MAX) return COFFEE_E_UNSUPPORTED;
@@ -717,7 +793,8 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
         const int q = s.quad_degree >= 0 ? s.quad_degree : 2 * s.degree;
         if (q > 10) return COFFEE_E_INVALID_ARG;
         const void* rf = nullptr;
-        coffee_status st = get_rtable_public(devid, s.form, s.cell, s.degree, q, 1, precision, &rf);
+        coffee_status st = na ? noalloc_table(*na, 0, s.form, s.cell, s.degree, q, precision, &rf)
+                              : get_rtable_public(devid, s.form, s.cell, s.degree, q, 1, precision, &rf);
         if (st != COFFEE_OK) return st;
         const int ns = n_scalar(s.cell, s.degree);
         dev::BinDesc& d = a.bins[b];
@@ -728,7 +805,13 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
         d.rfrag = rf;
         d.r64 = nullptr;
         if (s.degree == 1) {
-            st = reference_table_f64(devid, s.form, s.cell, 1, q, 1, &d.r64);
+            if (na) {
+                const void* r = nullptr;
+                st = noalloc_table(*na, 1, s.form, s.cell, 1, q, COFFEE_FP64, &r);
+                d.r64 = static_cast<const double*>(r);
+            } else {
+                st = reference_table_f64(devid, s.form, s.cell, 1, q, 1, &d.r64);
+            }
             if (st != COFFEE_OK) return st;
         }
         d.type = type;
@@ -818,4 +901,20 @@ extern "C" coffee_status coffee_assemble_batch_packed(int precision, const coffe
 
 extern "C" int64_t coffee_batch_workspace_size(int nseg, int64_t nentries) {
     return coffee::batch_workspace_bytes(nseg, nentries);
+}
+
+extern "C" coffee_status coffee_assemble_batch_packed_noalloc(int precision, const coffee_segment* segs, int nseg,
+                                                              const int32_t* seg_of, const int64_t* cell_of,
+                                                              int64_t nentries, void* out, int64_t* out_offset,
+                                                              void* hip_stream) {
+    using namespace coffee;
+    if (nentries > kScratchMaxEntries) return COFFEE_E_BUFFER_TOO_SMALL;
+    if (nentries < 0) return COFFEE_E_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return COFFEE_E_HIP;
+    NoallocDev* na = nullptr;
+    const coffee_status st = noalloc_device(dev, &na);
+    if (st != COFFEE_OK) return st;
+    return assemble_batch(precision, segs, nseg, seg_of, cell_of, nullptr, out_offset, 1, nentries, out, na->scratch,
+                          kScratchBytes, hip_stream, na);
 }

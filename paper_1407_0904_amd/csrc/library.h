@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "../../include/coffee.h"
 
@@ -29,6 +30,9 @@ coffee_status reference_table_f64(int dev, int form, int dim, int p, int q, int 
 coffee_status assemble_p1(int form, int cell, int fd, int q, int precision, const double* coords, const int32_t* c2v,
                           int64_t ncells, const coffee_field* coeffs, int ncoeff, void* out, void* hip_stream);
 coffee_status get_rtable_public(int dev, int form, int dim, int p, int q, int fd, int prec, const void** out);
+// Host bytes of the packed reference fragments and of the FP64 reference tensors.
+bool rtable_bytes(int form, int dim, int p, int q, int fd, int prec, std::vector<char>& buf);
+bool r64_table(int form, int dim, int p, int q, int fd, std::vector<double>& h);
 int batch_grid_mult();
 int tuned_grid_mult(int form, int cell, int degree, int fd, int prec);
 bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* task_cells);

@@ -143,6 +143,15 @@ static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym, 
     return buf;
 }
 
+// Packed reference fragments of a key (host bytes, in the layout the engines read).
+bool rtable_bytes(int form, int dim, int p, int q, int fd, int prec, std::vector<char>& buf) {
+    RefTensor R;
+    if (!build_reference(form, dim, p, q, fd, R)) return false;
+    const int rpg = dev::vec_rows_per_group(R.NS, dev::vec_group_tiles(form, prec));
+    buf = pack_fragments(R, prec, uses_scalar_engine(form), rpg);
+    return true;
+}
+
 // Reference fragments for a key, built and uploaded on first use.
 static coffee_status get_rtable(int dev, int form, int dim, int p, int q, int fd, int prec, const void** out) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -153,10 +162,8 @@ static coffee_status get_rtable(int dev, int form, int dim, int p, int q, int fd
         *out = it->second.ptr;
         return COFFEE_OK;
     }
-    RefTensor R;
-    if (!build_reference(form, dim, p, q, fd, R)) return COFFEE_E_INVALID_ARG;
-    const int rpg = dev::vec_rows_per_group(R.NS, dev::vec_group_tiles(form, prec));
-    std::vector<char> buf = pack_fragments(R, prec, uses_scalar_engine(form), rpg);
+    std::vector<char> buf;
+    if (!rtable_bytes(form, dim, p, q, fd, prec, buf)) return COFFEE_E_INVALID_ARG;
     DevTable t;
     t.bytes = buf.size();
     if (hipMalloc(&t.ptr, t.bytes) != hipSuccess) return COFFEE_E_NOMEM;

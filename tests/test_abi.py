@@ -130,3 +130,15 @@ def test_batch_workspace_size_checked_on_host(lib):
         dummy = C.c_void_p(16)  # never dereferenced
         assert f(1, dummy, 1, dummy, dummy, dummy, 1000, dummy, dummy, need - 1, None) == 3
         assert f(1, dummy, 17, dummy, dummy, dummy, 1000, dummy, dummy, need, None) == 1
+
+
+def test_noalloc_batch_limit_checked_on_host(lib):
+    """The allocation-free batch rejects more entries than its static scratch
+    array holds (status 3) before any HIP call."""
+    f = lib.coffee_assemble_batch_packed_noalloc
+    f.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                  C.c_void_p]
+    f.restype = C.c_int
+    dummy = C.c_void_p(16)  # never dereferenced
+    assert f(1, dummy, 1, dummy, dummy, 4194304 + 1, dummy, dummy, None) == 3
+    assert f(1, dummy, 1, dummy, dummy, -1, dummy, dummy, None) == 1
