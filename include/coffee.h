@@ -80,6 +80,17 @@ typedef enum {
                           accumulation; FP32 output                                             */
 } coffee_precision;
 
+/* Quadrature rule families. A quad_degree argument is q (collapsed
+ * Gauss-Jacobi rule of degree q, 0 <= q <= 10) or COFFEE_QUAD(q, rule).
+ * COFFEE_RULE_SYMMETRIC selects the fully symmetric rule of degree q,
+ * 0 <= q <= 6, of the kind the paper's kernels use (a 3-point rule in
+ * Listing 1, a 5-point rule in Listing 2): points in orbits of the simplex's
+ * symmetry group, one weight per orbit, found from the moment equations.
+ * Points per rule for q = 1..6: triangle 1, 3, 6, 6, 7, 12; tetrahedron 1, 4,
+ * 5, 14, 14, 24 (the tetrahedral 5-point rule has a negative weight). */
+typedef enum { COFFEE_RULE_GAUSS_JACOBI = 0, COFFEE_RULE_SYMMETRIC = 1 } coffee_rule;
+#define COFFEE_QUAD(q, rule) ((q) + 16 * (rule))
+
 /* A coefficient field on the cells (device pointers).
  * cell_to_dof != NULL: values is global [ndofs][ncomp], cell_to_dof is
  *   [ncells][nloc] int32 with nloc the Lagrange dof count of `degree`.
@@ -97,8 +108,9 @@ typedef struct {
  * and 2 declare, and Table 1). Buffers are caller-owned host memory; pass NULL
  * for all four to query *nq and *ndof. Layouts: points [nq][d], weights [nq],
  * basis [nq][ndof], dbasis [d][nq][ndof] (reference derivatives).
- * Errors: COFFEE_E_INVALID_ARG (bad cell, degree outside 0..4, quad_degree
- * outside 0..10, null nq/ndof). */
+ * quad_degree: q or COFFEE_QUAD(q, rule).
+ * Errors: COFFEE_E_INVALID_ARG (bad cell, degree outside 0..4, a quad_degree
+ * naming no rule, null nq/ndof). */
 coffee_status coffee_tabulate(int cell, int degree, int quad_degree, int* nq, int* ndof,
                               double* points, double* weights, double* basis, double* dbasis);
 

@@ -13,7 +13,8 @@
  * loops). Algorithms used here, each chosen for being easy to check by eye:
  *   - Gauss-Jacobi nodes by Newton iteration with deflation on the
  *     three-term recurrence; weights from the classical closed formula;
- *   - Stroud's collapsed (Duffy) product rule on the simplex;
+ *   - Stroud's collapsed (Duffy) product rule on the simplex, or a fully
+ *     symmetric rule from the moment equations (symrule.c);
  *   - Lagrange basis by Silvester's product formula in barycentric
  *     coordinates, gradients by the product rule;
  *   - inverse Jacobian by Gauss-Jordan elimination with partial pivoting;
@@ -117,7 +118,11 @@ static int rule_points_per_dir(int q) { return (q + 2) / 2; }   /* ceil((q+1)/2)
 /* Points X[nq][dim], weights W[nq]; lexicographic, first direction outermost.
  * Triangle: X = (u, (1-u) v), u ~ (1-u)^1, v ~ 1.
  * Tetrahedron: X = (u, (1-u) v, (1-u)(1-v) w), u ~ (1-u)^2, v ~ (1-v)^1, w ~ 1. */
-static int simplex_rule(int dim, int q, int* nq, double* X, double* W) {
+static int simplex_rule(int dim, int quad, int* nq, double* X, double* W) {
+    /* quad = q + 16 * rule: rule 1 is the fully symmetric rule (symrule.c) */
+    int q = quad & 15, rule = quad >> 4;
+    if (rule == 1) return oracle_symmetric_rule(dim, q, nq, X, W);
+    if (rule != 0 || q > 10) return OR_E_INVALID_ARG;
     int m = rule_points_per_dir(q);
     double xu[16], wu[16], xv[16], wv[16], xw[16], ww[16];
     if (dim == 2) {
@@ -247,7 +252,7 @@ static int nscalar(int dim, int p) {
 int oracle_tabulate(int dim, int degree, int quad_degree, int* nq, int* ndof,
                     double* points, double* weights, double* basis, double* dbasis) {
     if ((dim != 2 && dim != 3) || degree < 0 || degree > MAXP || !nq || !ndof) return OR_E_INVALID_ARG;
-    if (quad_degree < 0 || quad_degree > 10) return OR_E_INVALID_ARG;
+    if (quad_degree < 0) return OR_E_INVALID_ARG;
     int alpha[MAXN][4];
     int n = lattice_nodes(dim, degree, alpha);
     double X[MAXQ * 3], W[MAXQ];

@@ -50,6 +50,12 @@ int oracle_tabulate(int dim, int degree, int quad_degree, int* nq, int* ndof,
  * degree-p Lagrange element at arbitrary reference points X[npts][dim]. */
 int oracle_basis_at(int dim, int degree, int npts, const double* X, double* phi, double* dphi);
 
+/* Fully symmetric rule of degree q (0..6) on the reference simplex, solved
+ * from the moment equations (symrule.c): *nq points X[nq][dim], weights
+ * W[nq]; X and W may be NULL. A quad_degree argument of the other routines
+ * selects it as q + 16 (q alone: the collapsed Gauss-Jacobi rule). */
+int oracle_symmetric_rule(int dim, int q, int* nq, double* X, double* W);
+
 /* One-dimensional Gauss-Jacobi rule on [0,1] for weight (1-x)^alpha. */
 int oracle_gauss_jacobi(int m, int alpha, double* x, double* w);
 

@@ -20,11 +20,11 @@ FORMS = {"mass": 0, "helmholtz": 1, "elasticity": 2, "burgers": 3,
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc -O2 and OpenMP."""
-    src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(
-            os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "element.inc"))):
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "symrule.c")]
+    deps = srcs + [os.path.join(_HERE, f) for f in ("element.inc", "oracle.h")]
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in deps):
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-               "-o", _SO + ".tmp", src, "-lm"]
+               "-o", _SO + ".tmp", *srcs, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_SO + ".tmp", _SO)
     return _SO
@@ -48,6 +48,7 @@ def lib():
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_basis_at.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_gauss_jacobi.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+        L.oracle_symmetric_rule.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
         L.oracle_tensor_dim.argtypes = [C.c_int, C.c_int, C.c_int]
         L.oracle_assemble.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int64,
                                       C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
@@ -77,6 +78,25 @@ def gauss_jacobi(m: int, alpha: int):
     if st:
         raise OracleError(st)
     return x, w
+
+
+RULE_SYMMETRIC = 1
+
+
+def quad(q: int, rule: int = 0) -> int:
+    """quad_degree argument selecting rule `rule` of degree q (q + 16 rule)."""
+    return q + 16 * rule
+
+
+def symmetric_rule(dim: int, q: int):
+    """(points [nq, dim], weights [nq]) of the fully symmetric rule of degree q."""
+    nq = C.c_int()
+    X = np.zeros((64, dim))
+    W = np.zeros(64)
+    st = lib().oracle_symmetric_rule(dim, q, C.byref(nq), _ptr(X), _ptr(W))
+    if st:
+        raise OracleError(st)
+    return X[:nq.value].copy(), W[:nq.value].copy()
 
 
 def tabulate(dim: int, degree: int, quad_degree: int):

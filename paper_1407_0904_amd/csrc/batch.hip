@@ -791,7 +791,7 @@ static coffee_status assemble_batch(int precision, const coffee_segment* segs, i
         if (s.task_cells != 0 && (s.task_cells % 64 != 0 || s.task_cells < 64 || s.task_cells > 1024))
             return COFFEE_E_INVALID_ARG;
         const int q = s.quad_degree >= 0 ? s.quad_degree : 2 * s.degree;
-        if (q > 10) return COFFEE_E_INVALID_ARG;
+        if (rule_size(s.cell, q) <= 0) return COFFEE_E_INVALID_ARG;
         const void* rf = nullptr;
         coffee_status st = na ? noalloc_table(*na, 0, s.form, s.cell, s.degree, q, precision, &rf)
                               : get_rtable_public(devid, s.form, s.cell, s.degree, q, 1, precision, &rf);

@@ -252,7 +252,8 @@ coffee_status coffee::validate_common(int form, int cell, int degree, int quad_d
     if (form < COFFEE_MASS || form > COFFEE_SVK_JACOBIAN) return COFFEE_E_INVALID_ARG;
     if (cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) return COFFEE_E_INVALID_ARG;
     if (degree < 1 || degree > kMaxP) return COFFEE_E_INVALID_ARG;
-    if (quad_degree > 10) return COFFEE_E_INVALID_ARG;
+    // quad_degree: q or COFFEE_QUAD(q, rule); negative selects the default
+    if (quad_degree >= 0 && rule_size(cell == COFFEE_TRIANGLE ? 2 : 3, quad_degree) <= 0) return COFFEE_E_INVALID_ARG;
     if (ncells < 0 || nvert < 0 || nvert > INT32_MAX) return COFFEE_E_INVALID_ARG;
     if (ncells > 0 && (!coords || !c2v)) return COFFEE_E_INVALID_ARG;
     if (ncoeff < 0 || ncoeff > 2 || (ncoeff > 0 && !coeffs)) return COFFEE_E_INVALID_ARG;
@@ -286,7 +287,7 @@ coffee_status coffee::validate_common(int form, int cell, int degree, int quad_d
             fd = coeffs[0].degree;
     }
     int q = quad_degree >= 0 ? quad_degree : (form == COFFEE_BURGERS ? 2 * degree + 1 : 2 * degree);
-    if (q > 10) return COFFEE_E_UNSUPPORTED;
+    if (rule_size(d, q) <= 0) return COFFEE_E_UNSUPPORTED;
     *q_out = q;
     *fd_out = fd;
     return COFFEE_OK;

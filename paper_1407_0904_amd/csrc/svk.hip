@@ -855,8 +855,13 @@ static coffee_status svk_table(int dev, int dim, int p, int q, const double** ou
         *out = (const double*)it->second;
         return COFFEE_OK;
     }
+    // The SVK integrands at q = 2p are polynomials of degree exactly 2p on an
+    // affine cell (F is of degree p - 1), so every rule exact to degree q
+    // gives the same integral up to rounding: P2 uses the fully symmetric
+    // rule (6 points on triangles, 14 on tetrahedra, against 9 and 27 for the
+    // collapsed Gauss-Jacobi rule of that degree).
     Tables t;
-    if (!t.init(dim, p, q)) return COFFEE_E_INVALID_ARG;
+    if (!t.init(dim, p, p == 2 ? COFFEE_QUAD(q & 15, COFFEE_RULE_SYMMETRIC) : q)) return COFFEE_E_INVALID_ARG;
     std::vector<double> h;
     if (p == 1) {
         // P1 on an affine cell: the displacement gradient, hence the whole
@@ -934,10 +939,11 @@ hipError_t launch_svk(int form, int precision, const dev::SvkArgs& a, hipStream_
 hipError_t dispatch_svk(int form, int dim, int p, int q, int precision, const dev::SvkArgs& a, hipStream_t s,
                         int ncu, bool reverse, bool* found) {
     *found = true;
+    q &= 15;  // either rule family: the integrands are integrated exactly (svk_table)
     if (dim == 2 && p == 1 && q == 2) return launch_svk<2, 1, 1>(form, precision, a, s, ncu, reverse);
-    if (dim == 2 && p == 2 && q == 4) return launch_svk<2, 2, 9>(form, precision, a, s, ncu, reverse);
+    if (dim == 2 && p == 2 && q == 4) return launch_svk<2, 2, 6>(form, precision, a, s, ncu, reverse);
     if (dim == 3 && p == 1 && q == 2) return launch_svk<3, 1, 1>(form, precision, a, s, ncu, reverse);
-    if (dim == 3 && p == 2 && q == 4) return launch_svk<3, 2, 27>(form, precision, a, s, ncu, reverse);
+    if (dim == 3 && p == 2 && q == 4) return launch_svk<3, 2, 14>(form, precision, a, s, ncu, reverse);
     *found = false;
     return hipSuccess;
 }

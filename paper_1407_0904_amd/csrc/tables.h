@@ -12,8 +12,13 @@ constexpr int kMaxP = 4;
 constexpr int kMaxN = 35;  // scalar P4 on a tetrahedron
 
 bool gauss_jacobi01(int m, int alpha, long double* x, long double* w);
-bool simplex_rule(int dim, int q, long double* X, long double* W);
-int rule_size(int dim, int q);
+// Quadrature degree arguments below are encoded as COFFEE_QUAD(q, rule):
+// q = quad & 15, rule = quad >> 4 (0 collapsed Gauss-Jacobi, 1 symmetric).
+bool simplex_rule(int dim, int quad, long double* X, long double* W);
+int rule_size(int dim, int quad);  // -1 if the rule does not exist
+// Fully symmetric rules (symrule.cpp), q <= 6.
+int symmetric_rule_size(int dim, int q);
+bool symmetric_rule(int dim, int q, long double* X, long double* W);
 int n_scalar(int dim, int p);
 int lagrange_nodes(int dim, int p, long double* pts);
 

@@ -107,12 +107,18 @@ int n_scalar(int dim, int p) {
     return dim == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
 }
 
-int rule_size(int dim, int q) {
+int rule_size(int dim, int quad) {
+    const int q = quad & 15, rule = quad >> 4;
+    if (rule == COFFEE_RULE_SYMMETRIC) return symmetric_rule_size(dim, q);
+    if (rule != COFFEE_RULE_GAUSS_JACOBI || q > 10) return -1;
     int m = (q + 2) / 2;
     return dim == 2 ? m * m : m * m * m;
 }
 
-bool simplex_rule(int dim, int q, ld* X, ld* W) {
+bool simplex_rule(int dim, int quad, ld* X, ld* W) {
+    const int q = quad & 15, rule = quad >> 4;
+    if (rule == COFFEE_RULE_SYMMETRIC) return symmetric_rule(dim, q, X, W);
+    if (rule != COFFEE_RULE_GAUSS_JACOBI || q > 10) return false;
     int m = (q + 2) / 2;
     ld xa[16], wa[16], xb[16], wb[16], xc[16], wc[16];
     if (dim == 2) {
@@ -275,6 +281,7 @@ bool Tables::init(int dim_, int p_, int q_) {
     if (!basis.init(dim, p)) return false;
     n = basis.n;
     nq = rule_size(dim, q);
+    if (nq <= 0) return false;
     X.assign(nq * dim, 0.0L);
     W.assign(nq, 0.0L);
     if (!simplex_rule(dim, q, X.data(), W.data())) return false;
@@ -296,8 +303,9 @@ bool Tables::init(int dim_, int p_, int q_) {
 extern "C" coffee_status coffee_tabulate(int cell, int degree, int quad_degree, int* nq, int* ndof,
                                          double* points, double* weights, double* basis, double* dbasis) {
     if ((cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) || !nq || !ndof) return COFFEE_E_INVALID_ARG;
-    if (degree < 0 || degree > coffee::kMaxP || quad_degree < 0 || quad_degree > 10) return COFFEE_E_INVALID_ARG;
+    if (degree < 0 || degree > coffee::kMaxP || quad_degree < 0) return COFFEE_E_INVALID_ARG;
     const int dim = cell;
+    if (coffee::rule_size(dim, quad_degree) <= 0) return COFFEE_E_INVALID_ARG;
     *nq = coffee::rule_size(dim, quad_degree);
     *ndof = coffee::n_scalar(dim, degree);
     if (!points && !weights && !basis && !dbasis) return COFFEE_OK;

@@ -142,3 +142,19 @@ def test_noalloc_batch_limit_checked_on_host(lib):
     dummy = C.c_void_p(16)  # never dereferenced
     assert f(1, dummy, 1, dummy, dummy, 4194304 + 1, dummy, dummy, None) == 3
     assert f(1, dummy, 1, dummy, dummy, -1, dummy, dummy, None) == 1
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("q", range(1, 7))
+def test_symmetric_rules_match_oracle(lib, oracle, d, q):
+    """The library's symmetric rules (Gauss-Newton on Cartesian moments) and
+    the oracle's (Gauss-Newton on barycentric moments, separate code) are the
+    same point sets with the same weights."""
+    from paper_1407_0904_amd import coffee as cf
+    Xo, Wo = oracle.symmetric_rule(d, q)
+    Xl, Wl, _, _ = cf.coffee_tabulate(d, 1, q + 16)
+    assert Wl.shape == Wo.shape
+    a = np.lexsort(np.c_[Xo, Wo].T[::-1])
+    b = np.lexsort(np.c_[Xl, Wl].T[::-1])
+    np.testing.assert_allclose(Xl[b], Xo[a], atol=1e-14)
+    np.testing.assert_allclose(Wl[b], Wo[a], rtol=1e-13, atol=1e-16)

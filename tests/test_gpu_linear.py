@@ -261,3 +261,35 @@ def test_check_geometry(cf):
     bad[37] = bad[37][[0, 2, 1, 3]]  # inverted orientation
     bad[200, 1] = bad[200, 0]        # collapsed
     assert cf.coffee_check_geometry(3, coords, bad) == 37
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("form,d,p,fd,q", [("helmholtz", 3, 2, 2, 4), ("mass", 2, 3, 1, 6), ("helmholtz", 3, 3, 1, 6),
+                                           ("burgers", 3, 1, 1, 3), ("elasticity", 3, 2, 1, 4)])
+def test_symmetric_rule_forms(cf, oracle, form, d, p, fd, q, prec):
+    """Forms integrated with the fully symmetric rule (COFFEE_QUAD(q, 1)),
+    against the oracle with its own symmetric rule. The coefficient mass terms
+    are under-integrated at these degrees, so they match only if both sides
+    use the same rule; the Burgers case is the paper's 5-point tetrahedral
+    rule (negative centroid weight)."""
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    rng = np.random.default_rng(300 + 10 * p + q)
+    mesh = I.make_mesh(d, 8 if d == 2 else 4, 0.15, rng)
+    qs = oracle.quad(q, oracle.RULE_SYMMETRIC)
+    cst = []
+    if form == "burgers":
+        flds = [_field_of_degree(mesh, p, rng, -1, 1, ncomp=d)]
+        cst = [0.7, 1.3]
+    elif form == "elasticity":
+        flds = [_field_of_degree(mesh, 1, rng, 1, 10), _field_of_degree(mesh, 1, rng, 1, 10)]
+    else:
+        flds = [_field_of_degree(mesh, fd, rng)]
+    ref = oracle.assemble(form, mesh, p, quad_degree=qs, fields=flds, constants=cst)
+    got = assemble_gpu(form, mesh, p, flds, constants=cst, quad_degree=qs, precision=prec).cpu().numpy()
+    err = cell_rel_err(got, ref)
+    print(f"{form} d{d} p{p} symmetric q{q} {prec}: {err:.3e}")
+    assert err < TOL[prec]
+    if form in ("helmholtz", "mass") and fd > 0:
+        # the Gauss-Jacobi rule of the same degree gives a different tensor
+        gj = oracle.assemble(form, mesh, p, quad_degree=q, fields=flds)
+        assert cell_rel_err(gj, ref) > 1e-10

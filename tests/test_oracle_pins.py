@@ -92,6 +92,79 @@ def test_paper_point_counts(oracle):
     assert oracle.tabulate(3, 1, 3)[1].shape[0] == 8
 
 
+SYM_POINTS = {2: {1: 1, 2: 3, 3: 6, 4: 6, 5: 7, 6: 12}, 3: {1: 1, 2: 4, 3: 5, 4: 14, 5: 14, 6: 24}}
+SYM_EXACT = {2: {1: 1, 2: 2, 3: 4, 4: 4, 5: 5, 6: 6}, 3: {1: 1, 2: 2, 3: 3, 4: 5, 5: 5, 6: 6}}
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("q", range(1, 7))
+def test_symmetric_rule_exact_on_monomials(oracle, d, q):
+    """The symmetric rule of degree q integrates every monomial up to its
+    exactness degree (a! b! c! / (a+b+c+d)!), has its points strictly inside
+    the simplex, its weights summing to |T| and positive (the tetrahedral
+    degree-3 rule excepted), and fails the first monomial above that degree
+    (so the degree claimed is the degree reached)."""
+    Xq, W = oracle.symmetric_rule(d, q)
+    assert W.shape[0] == SYM_POINTS[d][q]
+    bary = np.c_[1 - Xq.sum(axis=1), Xq]
+    assert np.all(bary > 1e-12)
+    if not (d == 3 and q == 3):
+        assert np.all(W > 0)
+    assert abs(W.sum() - 1.0 / factorial(d)) < 1e-15
+    ex = SYM_EXACT[d][q]
+    for e in X.monomials(d, ex + 1):
+        exact = np.prod([factorial(k) for k in e]) / factorial(sum(e) + d)
+        got = np.sum(W * np.prod(Xq ** np.array(e), axis=1))
+        if sum(e) <= ex:
+            assert abs(got - exact) <= 1e-14 * max(exact, 1e-3), (e, got, exact)
+    worst = max(abs(np.sum(W * np.prod(Xq ** np.array(e), axis=1))
+                    - np.prod([factorial(k) for k in e]) / factorial(sum(e) + d))
+                for e in X.monomials(d, ex + 1) if sum(e) == ex + 1)
+    assert worst > 1e-8
+
+
+def test_symmetric_rule_orbits(oracle):
+    """Every point's barycentric coordinates, permuted, give another point of
+    the rule with the same weight (full symmetry)."""
+    from itertools import permutations
+    for d in (2, 3):
+        for q in range(1, 7):
+            Xq, W = oracle.symmetric_rule(d, q)
+            bary = np.c_[1 - Xq.sum(axis=1), Xq]
+            for i in range(len(W)):
+                for perm in permutations(range(d + 1)):
+                    b = bary[i, list(perm)]
+                    j = np.argmin(np.abs(bary - b).sum(axis=1))
+                    assert np.abs(bary[j] - b).max() < 1e-13 and abs(W[j] - W[i]) < 1e-15
+
+
+def test_paper_symmetric_point_counts(oracle):
+    """Listing 1 declares W[3] for the degree-2 triangle rule and Listing 2
+    W[5] for the P1 Burgers tetrahedron (degree 3): the symmetric rules of
+    those degrees have exactly 3 and 5 points (the 5-point rule's centroid
+    weight is negative, -2/15 of the reference volume's 6-fold)."""
+    assert oracle.symmetric_rule(2, 2)[1].shape[0] == 3
+    X5, W5 = oracle.symmetric_rule(3, 3)
+    assert W5.shape[0] == 5
+    assert abs(W5[np.argmin(np.abs(X5 - 0.25).sum(axis=1))] + 2.0 / 15.0) < 1e-15
+    # the degree-2 triangle rule: the points (1/6, 1/6), (2/3, 1/6), (1/6, 2/3), weight 1/6 each
+    X3, W3 = oracle.symmetric_rule(2, 2)
+    assert np.allclose(np.sort(X3[:, 0]), [1 / 6, 1 / 6, 2 / 3]) and np.allclose(W3, 1 / 6)
+
+
+@pytest.mark.parametrize("d,p", [(2, 2), (3, 2), (3, 3)])
+def test_symmetric_rule_assembly_exact(oracle, d, p):
+    """Mass and Helmholtz at degree 2p through the symmetric rule are exact,
+    like the Gauss-Jacobi rule; the coefficient mass at degree 2p + 1 too."""
+    rng = np.random.default_rng(70 + 10 * d + p)
+    v = rational_cell(d, rng)
+    cell = X.Cell(v)
+    m = I.single_cell_mesh(d, v)
+    qs = oracle.quad(2 * p, oracle.RULE_SYMMETRIC)
+    assert rel(oracle.assemble("mass", m, p, quad_degree=qs)[0], X.mass(cell, p)) < 1e-12
+    assert rel(oracle.assemble("helmholtz", m, p, quad_degree=qs)[0], X.mass(cell, p, stiff=True)) < 1e-12
+
+
 # ---------------------------------------------------------------- basis
 
 @pytest.mark.parametrize("d,p", [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3), (3, 4)])
