@@ -38,6 +38,10 @@ int tuned_grid_mult(int form, int cell, int degree, int fd, int prec);
 bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* task_cells);
 bool tuned_packed(int form, int cell, int degree, int prec, int* task_cells);
 void free_svk_tables();
+coffee_status assemble_svk_bf16(int form, int cell, int degree, int q, const double* coords, const int32_t* c2v,
+                                int64_t ncells, const coffee_field* coeffs, const double* constants, int nconst,
+                                void* out, void* hip_stream);
+void free_svkb_tables();
 int num_cu(int dev);
 
 // Deterministic scatter of per-cell gradients (scatter.hip). One target array:

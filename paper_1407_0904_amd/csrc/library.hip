@@ -402,6 +402,7 @@ extern "C" coffee_status coffee_check_geometry(int cell, const double* coords, i
 extern "C" void coffee_shutdown(void) {
     free_adjoint_tables();
     free_svk_tables();
+    free_svkb_tables();
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);

@@ -974,7 +974,9 @@ coffee_status assemble_svk(int form, int cell, int degree, int q, int precision,
                            const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, const double* constants,
                            int nconst, void* out, void* hip_stream) {
     (void)nvert;
-    if (precision == COFFEE_BF16X3) return COFFEE_E_UNSUPPORTED;
+    if (precision == COFFEE_BF16X3)
+        return assemble_svk_bf16(form, cell, degree, q, coords, c2v, ncells, coeffs, constants, nconst, out,
+                                 hip_stream);
     if (ncells == 0) return COFFEE_OK;
     dev::SvkArgs a;
     const double* tab = nullptr;

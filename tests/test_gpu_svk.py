@@ -24,7 +24,7 @@ def _disp(mesh, p, rng, sigma=0.05):
     return I.Field(rng.normal(0, sigma, (nd, d)), c2d, 2, d)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("form", ["svk_energy", "svk_residual", "svk_jacobian"])
 @pytest.mark.parametrize("d,p", [(3, 1), (3, 2), (2, 1), (2, 2)])
 def test_svk_forward(cf, oracle, form, d, p, prec):
@@ -40,13 +40,26 @@ def test_svk_forward(cf, oracle, form, d, p, prec):
     assert err < TOL[prec]
 
 
-def test_svk_bf16x3_reported_unsupported(cf):
-    from gpu_util import assemble_gpu
-    rng = np.random.default_rng(1)
-    mesh = I.make_mesh(3, 2, 0.1, rng)
-    with pytest.raises(cf.CoffeeError) as ei:
-        assemble_gpu("svk_jacobian", mesh, 1, [_disp(mesh, 1, rng)], precision="bf16x3")
-    assert ei.value.code == 2
+@pytest.mark.parametrize("form", ["svk_energy", "svk_residual", "svk_jacobian"])
+@pytest.mark.parametrize("d,p", [(3, 2), (3, 1), (2, 2)])
+def test_svk_bf16x3_ragged_counts(cf, oracle, form, d, p):
+    """BF16X3 SVK at cell counts around the 16-cell tile and the Jacobian's
+    staging rounds, with the displacement through a dof map and cell-major."""
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    rng = np.random.default_rng(90 + 10 * d + p)
+    mesh = I.make_mesh(d, 9 if d == 2 else 4, 0.1, rng)
+    u = _disp(mesh, p, rng)
+    ucm = I.Field(np.ascontiguousarray(u.values[u.cell_to_dof]), None, u.degree, u.ncomp)
+    cst = [1.1, 0.9]
+    for count in (1, 7, 15, 16, 17, 40, 131):
+        sub = I.Mesh(mesh.d, mesh.n, mesh.coords, np.ascontiguousarray(mesh.cells[:count]))
+        ref = oracle.assemble(form, mesh, p, fields=[u], constants=cst, cells=np.arange(count))
+        mapped = I.Field(u.values, np.ascontiguousarray(u.cell_to_dof[:count]), u.degree, u.ncomp)
+        cellmajor = I.Field(np.ascontiguousarray(ucm.values[:count]), None, u.degree, u.ncomp)
+        for f in (mapped, cellmajor):
+            got = assemble_gpu(form, sub, p, [f], constants=cst, precision="bf16x3").cpu().numpy()
+            err = cell_rel_err(got.reshape(count, -1), ref.reshape(count, -1))
+            assert err < TOL["bf16x3"], (count, f.cell_to_dof is None, err)
 
 
 @pytest.mark.parametrize("d,p", [(3, 1), (3, 2), (2, 2)])
@@ -86,7 +99,7 @@ def test_svk_full_size_sampled(cf, oracle):
     idx = torch.as_tensor(sample, device=coords.device)
     for form in ("svk_energy", "svk_residual", "svk_jacobian"):
         ref = oracle.assemble(form, w.mesh, 2, fields=w.fields, constants=w.constants, cells=sample)
-        for prec in ("fp64", "fp32"):
+        for prec in ("fp64", "fp32", "bf16x3"):
             out = cf.coffee_assemble(form, 3, 2, coords, c2v, coeffs=dfs, constants=w.constants, precision=prec)
             torch.cuda.synchronize()
             got = out[idx].cpu().numpy()
