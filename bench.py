@@ -67,35 +67,75 @@ def algorithmic_bytes(w, out_elems: int, out_elem: int) -> int:
     return int(b + out_elems * out_elem)
 
 
-def algorithmic_flops(w) -> float:
-    """Flops per cell of the formulation each kernel implements.
+# Peaks (MI355X published figures): HBM 8 TB/s; FP64 vector and matrix 78.6
+# TFLOP/s; FP32 vector and matrix 157.3 TFLOP/s; dense BF16 matrix 2.5 PFLOP/s,
+# of which BF16X3 spends three products per useful multiply-add.
+PEAK_TF = {"mfma_f64": 78.6, "mfma_f32": 157.3, "mfma_bf16x3": 2500.0 / 3.0, "valu_f64": 78.6, "valu_f32": 157.3}
+
+
+def svk_work(d: int, p: int, form: str, prec: str) -> dict:
+    """Flops per cell (2 per multiply-add) that each SVK kernel executes, by
+    the unit that executes them. Points: 1 at P1 (the integrand is constant),
+    the symmetric rule at P2 (6 triangle / 14 tetrahedron points)."""
+    ns, D, nb = n_scalar(d, p), d, d * (d + 1) // 2
+    nq = 1 if p == 1 else {2: 6, 3: 14}[d]
+    U = 2 * D * D * ns                                   # reference displacement gradient
+    pt = 2 * D ** 3 + D * D * (2 * D + 2) + 3 * D * D + 2 * D * D   # H = U K, E, S, psi
+    P = 2 * D ** 3                                       # P = F S
+    if prec in ("fp64", "fp32"):
+        unit = "valu_f64" if prec == "fp64" else "valu_f32"
+        if form == "svk_energy":
+            return {unit: nq * (U + pt + P)}
+        if form == "svk_residual":
+            return {unit: nq * (U + pt + P + 2 * D ** 3 + 2 * D * D * ns)}
+        # Jacobian: F, S and S^ = K S K^T once per (cell, point); per block
+        # k1, k2, F.F, H, the row products dphi^T H and the rank updates of the
+        # block's n x n entries
+        per_pt = U + 2 * D ** 3 + D * D * (2 * D + 2) + 3 * D * D + 2 * D ** 3 + nb * 2 * D * D
+        per_blk = 4 * D * D + 2 * D + 8 * D * D + 2 * D * D * ns + 2 * D * ns * ns
+        if prec == "fp64":
+            return {"valu_f64": nq * (per_pt + nb * per_blk)}
+        # FP32 mode: point data in FP64, the block accumulation in FP32
+        return {"valu_f64": nq * (per_pt + nb * (4 * D * D + 2 * D + 8 * D * D)),
+                "valu_f32": nq * nb * (2 * D * D * ns + 2 * D * ns * ns)}
+    # BF16X3: useful multiply-adds of the contractions on the matrix cores,
+    # point arithmetic in FP32 on the vector units
+    interp = 2 * ns * (nq * D) * D
+    if form == "svk_energy":
+        return {"mfma_bf16x3": interp, "valu_f32": nq * pt}
+    if form == "svk_residual":
+        return {"mfma_bf16x3": interp + 2 * (nq * D) * ns * D, "valu_f32": nq * (pt + P + 2 * D ** 3)}
+    kj = nq * D * D
+    return {"mfma_bf16x3": interp + nb * 2 * kj * ns * ns,
+            "valu_f32": nq * (pt + P + 4 * D ** 3 + 2 * D * D) + nb * kj * 10}
+
+
+def work_model(w, prec: str) -> dict:
+    """Flops per cell of the formulation each kernel implements, by unit.
 
     Linear forms: the q-collapsed contraction, 2 * K * (entries computed), K =
     number of geometry-tensor terms per block (mass and Helmholtz compute the
-    upper triangle only; elasticity and Burgers every block). St Venant-Kirchhoff: the
-    per-point evaluation in physical space (deformation gradient, physical
-    basis gradients, stress, and for the Jacobian the upper blocks of the
-    tangent product)."""
+    upper triangle only; elasticity and Burgers every block), on the matrix
+    cores of the precision (degree-1 mass and Helmholtz in FP64/FP32 on the
+    vector units). St Venant-Kirchhoff: svk_work."""
     d, p, form = w.mesh.d, w.degree, w.form
+    if form.startswith("svk"):
+        return svk_work(d, p, form, prec)
     ns = n_scalar(d, p)
     nd = d * (d + 1) // 2
     fd = w.fields[0].degree if w.fields else 0
     nf = n_scalar(d, fd) if fd else 0
     if form == "mass":
-        return 2.0 * nf * ns * (ns + 1) / 2
-    if form == "helmholtz":
-        return 2.0 * (nf + nd) * ns * (ns + 1) / 2
-    if form == "elasticity":
-        return 2.0 * (nf * d * d) * (d * ns) ** 2
-    if form == "burgers":
-        return 2.0 * (1 + nd + 2 * nf * d) * (d * ns) ** 2
-    nq = {1: 8, 2: 27}[p] if d == 3 else {1: 4, 2: 9}[p]
-    pt = 2 * d * d * ns + 2 * d * d * ns + 60
-    if form == "svk_residual":
-        pt += 2 * d * d * ns
-    if form == "svk_jacobian":
-        pt += nd * (2 * d * d * ns + 2 * d * ns * ns + 30)
-    return float(nq * pt)
+        f = 2.0 * max(nf, 1) * ns * (ns + 1) / 2
+    elif form == "helmholtz":
+        f = 2.0 * (nf + nd) * ns * (ns + 1) / 2
+    elif form == "elasticity":
+        f = 2.0 * (max(nf, 1) * d * d) * (d * ns) ** 2
+    else:
+        f = 2.0 * (1 + nd + 2 * nf * d) * (d * ns) ** 2
+    if p == 1 and form in ("mass", "helmholtz") and prec != "bf16x3":
+        return {"valu_f64" if prec == "fp64" else "valu_f32": f}
+    return {{"fp64": "mfma_f64", "fp32": "mfma_f32", "bf16x3": "mfma_bf16x3"}[prec]: f}
 
 
 def cell_rel_err(got, ref):
@@ -176,12 +216,15 @@ class Ctx:
         return coords, c2v, fields
 
 
-def roof(nbytes, flops, kms, prec):
-    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9) * 1e3
-    t_fl = flops / (FLOP_PEAK_TF[prec] * 1e12) * 1e3
-    bound = "hbm" if t_hbm >= t_fl else ("fp64" if prec == "fp64" else "fp32" if prec == "fp32" else "mfma-bf16")
-    return {"bound": bound, "frac": max(t_hbm, t_fl) / kms, "gbs": nbytes / (kms * 1e-3) / 1e9,
-            "gflops": flops / (kms * 1e-3) / 1e9, "t_bound_ms": max(t_hbm, t_fl)}
+def roof(nbytes, work, kms):
+    """Binding roofline: t_bound = max(bytes / HBM peak, flops_u / peak_u over
+    the units u doing the work); frac = t_bound / measured."""
+    t = {"hbm": nbytes / (HBM_PEAK_GBS * 1e9) * 1e3}
+    for unit, flops in work.items():
+        t[unit] = flops / (PEAK_TF[unit] * 1e12) * 1e3
+    bound = max(t, key=t.get)
+    return {"bound": bound, "frac": t[bound] / kms, "gbs": nbytes / (kms * 1e-3) / 1e9,
+            "gflops": sum(work.values()) / (kms * 1e-3) / 1e9, "t_bound_ms": t[bound]}
 
 
 def measure_forward(ctx, w, prec, sample_n=300, seed=3, tag=None):
@@ -192,24 +235,25 @@ def measure_forward(ctx, w, prec, sample_n=300, seed=3, tag=None):
     E = w.mesh.ncells
     shape = cf.output_shape(w.form, E, w.mesh.d, w.degree)
     out = torch.empty(shape, dtype=torch.float64 if prec == "fp64" else torch.float32, device=ctx.dev)
-    fn = lambda: cf.coffee_assemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields, constants=w.constants,
-                                    quad_degree=w.quad_degree, precision=prec, out=out)
+    fn = cf.PreparedAssemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields, constants=w.constants,
+                             quad_degree=w.quad_degree, precision=prec, out=out)
     ms, per = time_gpu(fn, ctx.steps, ctx.warmup)
     sample = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(seed).integers(0, E, sample_n)]))
     ref = O.assemble(w.form, w.mesh, w.degree, w.quad_degree, fields=w.fields, constants=w.constants, cells=sample)
     err = cell_rel_err(out[torch.as_tensor(sample, device=ctx.dev)].cpu().numpy(), ref)
     nbytes = algorithmic_bytes(w, int(np.prod(shape)), 8 if prec == "fp64" else 4)
-    flops = algorithmic_flops(w) * E
+    work = {k: v * E for k, v in work_model(w, prec).items()}
+    flops = sum(work.values())
     del out, coords, c2v, fields
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    r = roof(nbytes, flops, float(per.mean()), prec)
+    r = roof(nbytes, work, float(per.mean()))
     log(f"{tag or w.name} {w.form} {prec}: {per.mean() * 1e3:.1f} us, {r['gbs']:.0f} GB/s, frac {r['frac']:.2f}, "
         f"err {err:.2e}")
     return {"workload": tag or w.name, "form": w.form, "cells": E, "precision": prec,
             "ms_per_step": ms, "kernel_ms": pct(per), "cells_per_s": E / (ms * 1e-3),
-            "algorithmic_bytes": nbytes, "algorithmic_flops": flops, "gbs": r["gbs"], "gflops": r["gflops"],
-            "bound": r["bound"], "frac": r["frac"], "max_cell_rel_err": err}
+            "algorithmic_bytes": nbytes, "algorithmic_flops": flops, "flops_by_unit": work, "gbs": r["gbs"],
+            "gflops": r["gflops"], "bound": r["bound"], "frac": r["frac"], "max_cell_rel_err": err}
 
 
 def adjoint_flops_per_cell(w):
@@ -334,9 +378,12 @@ def mixed_batch_section(ctx):
         sub.append((form, d, p, c, v[cells].contiguous(), sf,
                     torch.empty((idx.size, ns, ns), dtype=torch.float32, device=dev)))
 
+    calls = [cf.PreparedAssemble(form, d, p, c, v, coeffs=[sf], precision="fp32", out=o)
+             for (form, d, p, c, v, sf, o) in sub]
+
     def per_bin():
-        for (form, d, p, c, v, sf, o) in sub:
-            cf.coffee_assemble(form, d, p, c, v, coeffs=[sf], precision="fp32", out=o)
+        for call in calls:
+            call()
 
     ms_sep, per_sep = time_gpu(per_bin, ctx.steps, ctx.warmup)
     del sub
@@ -382,7 +429,7 @@ def forms_section(ctx):
         w = I.workload(name)
         for form in ("svk_energy", "svk_residual", "svk_jacobian"):
             w.form = form
-            for prec in ("fp64", "fp32"):
+            for prec in ("fp64", "fp32", "bf16x3"):
                 res.append(measure_forward(ctx, w, prec, sample_n=150))
         w.form = "svk_energy"
         res.append(measure_adjoint(ctx, w, name))
@@ -441,8 +488,8 @@ def main():
                                                              if p != args.precision])
     for prec in precs:
         out = torch.empty(shape, dtype=torch.float64 if prec == "fp64" else torch.float32, device=dev)
-        fn = lambda: coffee.coffee_assemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields,
-                                            constants=w.constants, quad_degree=w.quad_degree, precision=prec, out=out)
+        fn = coffee.PreparedAssemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields,
+                                     constants=w.constants, quad_degree=w.quad_degree, precision=prec, out=out)
         ms, per = time_gpu(fn, args.steps, args.warmup)
         err = cell_rel_err(out[idx].cpu().numpy(), ref)
         nbytes = algorithmic_bytes(w, int(np.prod(shape)), 8 if prec == "fp64" else 4)

@@ -117,23 +117,28 @@ def _nloc(d: int, p: int) -> int:
 
 
 def _need(t, name, dtype, shape=None, numel=None, allow_none=False):
+    # `name` is a string or a callable giving it (formatted only for the error)
     if t is None:
         if allow_none:
             return
-        raise ValueError(f"{name} is required")
+        raise ValueError(f"{_nm(name)} is required")
     if not isinstance(t, torch.Tensor):
-        raise ValueError(f"{name} must be a torch tensor")
+        raise ValueError(f"{_nm(name)} must be a torch tensor")
     if t.dtype != dtype:
-        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
-    if shape is not None and tuple(t.shape) != tuple(shape):
-        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        raise ValueError(f"{_nm(name)} must be {dtype}, got {t.dtype}")
+    if shape is not None and t.shape != shape:
+        raise ValueError(f"{_nm(name)} has shape {tuple(t.shape)}, expected {tuple(shape)}")
     if numel is not None and t.numel() != numel:
-        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+        raise ValueError(f"{_nm(name)} has {t.numel()} elements, expected {numel}")
+
+
+def _nm(name):
+    return name() if callable(name) else name
 
 
 def _check_mesh(d, coords, cell_to_vertex, where=""):
-    _need(coords, where + "coords", torch.float64)
-    _need(cell_to_vertex, where + "cell_to_vertex", torch.int32)
+    _need(coords, lambda: where + "coords", torch.float64)
+    _need(cell_to_vertex, lambda: where + "cell_to_vertex", torch.int32)
     if coords.ndim != 2 or coords.shape[1] != d:
         raise ValueError(f"{where}coords has shape {tuple(coords.shape)}, expected (nvert, {d})")
     if cell_to_vertex.ndim != 2 or cell_to_vertex.shape[1] != d + 1:
@@ -142,18 +147,18 @@ def _check_mesh(d, coords, cell_to_vertex, where=""):
 
 def _check_fields(coeffs, d, ncells, where="coeffs"):
     for i, f in enumerate(coeffs):
-        name = f"{where}[{i}]"
-        _need(f.values, name + ".values", torch.float64)
-        if not 1 <= int(f.degree) <= 4 or int(f.ncomp) < 1:
+        name = lambda: f"{where}[{i}]"
+        _need(f.values, lambda: name() + ".values", torch.float64)
+        if not 1 <= f.degree <= 4 or f.ncomp < 1:
             continue  # the library reports the bad degree or component count
-        nloc, nc = _nloc(d, int(f.degree)), int(f.ncomp)
+        nloc, nc = _nloc(d, f.degree), f.ncomp
         if f.cell_to_dof is not None:
-            _need(f.cell_to_dof, name + ".cell_to_dof", torch.int32, shape=(ncells, nloc))
+            _need(f.cell_to_dof, lambda: name() + ".cell_to_dof", torch.int32, shape=(ncells, nloc))
             v = f.values
             if v.numel() % nc or (v.ndim >= 2 and v.shape[-1] != nc) or (v.ndim == 1 and nc != 1):
-                raise ValueError(f"{name}.values has shape {tuple(v.shape)}, expected (ndofs, {nc})")
+                raise ValueError(f"{name()}.values has shape {tuple(v.shape)}, expected (ndofs, {nc})")
         else:
-            _need(f.values, name + ".values", torch.float64, numel=ncells * nloc * nc)
+            _need(f.values, lambda: name() + ".values", torch.float64, numel=ncells * nloc * nc)
 
 
 @dataclass
@@ -199,12 +204,30 @@ def coffee_tensor_dim(form, cell, degree: int) -> int:
 
 
 def output_shape(form, ncells: int, cell, degree: int):
-    N = coffee_tensor_dim(form, cell, degree)
+    N = _tensor_dim(FORMS[form], CELLS[cell], degree)
     if form == "svk_energy":
         return (ncells,)
     if form == "svk_residual":
         return (ncells, N)
     return (ncells, N, N)
+
+
+_TDIM = {}
+
+
+def _tensor_dim(form: int, cell: int, degree: int) -> int:
+    key = (form, cell, degree)
+    n = _TDIM.get(key)
+    if n is None:
+        n = _TDIM[key] = _lib.coffee_tensor_dim(form, cell, degree)
+    return n
+
+
+def _numel(shape) -> int:
+    n = 1
+    for s in shape:
+        n *= s
+    return n
 
 
 def coffee_assemble(form, cell, degree: int, coords: torch.Tensor, cell_to_vertex: torch.Tensor,
@@ -222,7 +245,7 @@ def coffee_assemble(form, cell, degree: int, coords: torch.Tensor, cell_to_verte
     elif out is None:
         out = torch.empty(shape, dtype=odt, device=coords.device)
     else:
-        _need(out, "out", odt, numel=int(np.prod(shape)))
+        _need(out, "out", odt, numel=_numel(shape))
     cst = np.ascontiguousarray(constants, dtype=np.float64)
     st = _lib.coffee_assemble(FORMS[form], c, degree, quad_degree, PRECISIONS[precision],
                               _dptr(coords, torch.float64, "coords"), coords.shape[0] if coords.ndim else 0,
@@ -232,6 +255,41 @@ def coffee_assemble(form, cell, degree: int, coords: torch.Tensor, cell_to_verte
                               _dptr(out, odt, "out"), _stream(stream))
     _check(st, "coffee_assemble")
     return out
+
+
+class PreparedAssemble:
+    """One coffee_assemble call with its arguments checked and marshalled once,
+    for callers that launch the same assembly repeatedly (time stepping, a
+    serving loop, a benchmark): each call only re-enters the C ABI. The
+    tensors are kept referenced; the stream is the one current at preparation
+    unless given."""
+
+    def __init__(self, form, cell, degree: int, coords, cell_to_vertex, coeffs=(), constants=(),
+                 quad_degree: int = -1, precision: str = "fp64", out=None, stream=None):
+        c = CELLS[cell]
+        _check_mesh(c, coords, cell_to_vertex)
+        ncells = cell_to_vertex.shape[0]
+        _check_fields(coeffs, c, ncells)
+        odt = torch.float64 if precision == "fp64" else torch.float32
+        shape = output_shape(form, ncells, c, degree)
+        if min(shape) < 0:
+            raise CoffeeError(1, "PreparedAssemble")
+        if out is None:
+            out = torch.empty(shape, dtype=odt, device=coords.device)
+        _need(out, "out", odt, numel=_numel(shape))
+        self.out = out
+        self._keep = (coords, cell_to_vertex, list(coeffs), np.ascontiguousarray(constants, dtype=np.float64))
+        cst = self._keep[3]
+        self._fields = _fields(list(coeffs))
+        self._args = (FORMS[form], c, degree, quad_degree, PRECISIONS[precision],
+                      _dptr(coords, torch.float64, "coords"), coords.shape[0],
+                      _dptr(cell_to_vertex, torch.int32, "cell_to_vertex"), ncells,
+                      self._fields, len(coeffs), cst.ctypes.data if cst.size else None, cst.size,
+                      _dptr(out, odt, "out"), _stream(stream))
+
+    def __call__(self) -> torch.Tensor:
+        _check(_lib.coffee_assemble(*self._args), "coffee_assemble")
+        return self.out
 
 
 def coffee_adjoint_workspace_size(form, cell, degree: int, nvert: int, ncells: int, coeffs=()) -> int:
@@ -253,7 +311,7 @@ def coffee_assemble_adjoint(form, cell, degree: int, coords, cell_to_vertex, coe
     _check_mesh(c, coords, cell_to_vertex)
     ncells = cell_to_vertex.shape[0]
     _check_fields(coeffs, c, ncells)
-    N = coffee_tensor_dim(form, c, degree)
+    N = _tensor_dim(FORMS[form], c, degree)
     if N > 0:
         _need(lam, "lam", torch.float64, shape=(ncells, N), allow_none=True)
         _need(u, "u", torch.float64, shape=(ncells, N), allow_none=True)

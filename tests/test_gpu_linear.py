@@ -293,3 +293,18 @@ def test_symmetric_rule_forms(cf, oracle, form, d, p, fd, q, prec):
         # the Gauss-Jacobi rule of the same degree gives a different tensor
         gj = oracle.assemble(form, mesh, p, quad_degree=q, fields=flds)
         assert cell_rel_err(gj, ref) > 1e-10
+
+
+def test_prepared_assemble_equals_assemble(cf):
+    """PreparedAssemble (arguments checked and marshalled once) launches the
+    same kernel: bitwise equal to coffee_assemble, on repeated calls."""
+    import torch
+    from gpu_util import to_dev
+    w = I.workload("helmholtz_p2_tet", n=6)
+    coords, c2v, dfs = to_dev(w.mesh, w.fields)
+    ref = cf.coffee_assemble(w.form, 3, 2, coords, c2v, coeffs=dfs, quad_degree=w.quad_degree)
+    call = cf.PreparedAssemble(w.form, 3, 2, coords, c2v, coeffs=dfs, quad_degree=w.quad_degree)
+    for _ in range(3):
+        out = call()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
