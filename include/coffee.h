@@ -262,6 +262,48 @@ coffee_status coffee_assemble_batch_packed_noalloc(int precision, const coffee_s
                                                    int64_t nentries, void* out, int64_t* out_offset,
                                                    void* hip_stream);
 
+/* Global assembly (paper, section 2: the element tensors are the per-cell
+ * contributions summed into the matrix of the linear system; local assembly
+ * is the step before it).
+ *
+ * coffee_csr_pattern: the CSR sparsity pattern of that matrix for a space
+ * whose cells map to dofs through cell_to_dof (device int32 [ncells][nloc],
+ * values in [0, ndofs)); a vector space of ncomp components (1..3) numbers
+ * its global dofs dof * ncomp + c and every scalar nonzero becomes an
+ * ncomp x ncomp block. Every pair of dofs sharing a cell is a nonzero; rows
+ * hold their columns in increasing order. row_ptr: device int64
+ * [ndofs * ncomp + 1]; col_idx: device int32 of col_capacity entries. The
+ * call synchronises on hip_stream to learn the count: *nnz (host) always
+ * receives it, and if col_idx is NULL or col_capacity < *nnz the call
+ * returns COFFEE_E_BUFFER_TOO_SMALL without writing col_idx (call again with
+ * a large enough buffer). workspace: device, 256-byte aligned, at least
+ * coffee_csr_pattern_workspace_size bytes (the 64-bit keys of every
+ * (cell, i, j) pair, sorted). Deterministic.
+ * Errors: COFFEE_E_INVALID_ARG, COFFEE_E_UNSUPPORTED (ndofs * ncomp beyond
+ * int32), COFFEE_E_BUFFER_TOO_SMALL, COFFEE_E_HIP. */
+int64_t coffee_csr_pattern_workspace_size(int64_t ncells, int nloc, int64_t ndofs);
+coffee_status coffee_csr_pattern(const int32_t* cell_to_dof, int64_t ncells, int nloc, int64_t ndofs, int ncomp,
+                                 int64_t* row_ptr, int32_t* col_idx, int64_t col_capacity, int64_t* nnz,
+                                 void* workspace, int64_t workspace_bytes, void* hip_stream);
+
+/* coffee_assemble_csr: the global matrix sum_e P_e^T A_e P_e of a bilinear
+ * form (mass, Helmholtz, elasticity, Burgers, SVK Jacobian) in the CSR
+ * pattern built by coffee_csr_pattern for the form's space (cell_to_dof: the
+ * space's dof map, the one the pattern was built from; NULL at degree 1 means
+ * cell_to_vertex). The other arguments are coffee_assemble's. values (device,
+ * nnz entries, FP64 if precision is COFFEE_FP64, else FP32) is overwritten.
+ * The cells are assembled in chunks of 131,072 into `workspace` (16-byte
+ * aligned, coffee_assemble_csr_workspace_size bytes) and added to the matrix
+ * with atomic adds: sums of shared entries are order-dependent in the last
+ * bits. Errors: as coffee_assemble, plus COFFEE_E_BUFFER_TOO_SMALL. */
+int64_t coffee_assemble_csr_workspace_size(int form, int cell, int degree, int precision, int64_t ncells);
+coffee_status coffee_assemble_csr(int form, int cell, int degree, int quad_degree, int precision,
+                                  const double* coords, int64_t nvert, const int32_t* cell_to_vertex,
+                                  int64_t ncells, const coffee_field* coeffs, int ncoeff,
+                                  const double* constants, int nconst, const int32_t* cell_to_dof, int64_t ndofs,
+                                  const int64_t* row_ptr, const int32_t* col_idx, int64_t nnz, void* values,
+                                  void* workspace, int64_t workspace_bytes, void* hip_stream);
+
 /* Checks every cell for the geometry step of the per-cell kernel (section 2,
  * Fig. 1: the Jacobian of the affine map and its determinant, which the
  * kernels invert and use as |det J| without checking): writes to *first_bad

@@ -180,3 +180,27 @@ def adjoint(form: str, mesh, degree: int, quad_degree: int = -1, fields=(), cons
     if st:
         raise OracleError(st)
     return val.value, gc, gfs
+
+
+def assemble_global(form: str, mesh, degree: int, space_map, ndofs: int, quad_degree: int = -1, fields=(),
+                    constants=()):
+    """The global matrix sum_e P_e^T A_e P_e as a scipy CSR matrix (FP64):
+    element tensors from `assemble`, scattered entry by entry into a
+    coordinate list with the global indices dof * ncomp + c of the local dofs
+    (c, a) (component-blocked locally), duplicates summed by scipy.
+    space_map [E, nloc] is the dof map of the form's space."""
+    import scipy.sparse as sp
+    A = assemble(form, mesh, degree, quad_degree, fields=fields, constants=constants)
+    E, N, _ = A.shape
+    nloc = space_map.shape[1]
+    nc = N // nloc
+    gidx = np.empty((E, N), dtype=np.int64)
+    for c in range(nc):
+        for a in range(nloc):
+            gidx[:, c * nloc + a] = space_map[:, a].astype(np.int64) * nc + c
+    rows = np.repeat(gidx, N, axis=1).reshape(-1)
+    cols = np.tile(gidx, (1, N)).reshape(-1)
+    M = sp.coo_matrix((A.reshape(-1), (rows, cols)), shape=(ndofs * nc, ndofs * nc)).tocsr()
+    M.sum_duplicates()
+    M.sort_indices()
+    return M

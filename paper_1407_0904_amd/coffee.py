@@ -70,6 +70,15 @@ def _load():
     L.coffee_assemble_batch_packed_noalloc.restype = i32
     L.coffee_batch_workspace_size.argtypes = [i32, i64]
     L.coffee_batch_workspace_size.restype = i64
+    L.coffee_csr_pattern_workspace_size.argtypes = [i64, i32, i64]
+    L.coffee_csr_pattern_workspace_size.restype = i64
+    L.coffee_csr_pattern.argtypes = [vp, i64, i32, i64, i32, vp, vp, i64, C.POINTER(C.c_int64), vp, i64, vp]
+    L.coffee_csr_pattern.restype = i32
+    L.coffee_assemble_csr_workspace_size.argtypes = [i32, i32, i32, i32, i64]
+    L.coffee_assemble_csr_workspace_size.restype = i64
+    L.coffee_assemble_csr.argtypes = [i32, i32, i32, i32, i32, vp, i64, vp, i64, vp, i32, vp, i32, vp, i64, vp, vp,
+                                      i64, vp, vp, i64, vp]
+    L.coffee_assemble_csr.restype = i32
     L.coffee_load_tuning.argtypes = [C.c_char_p]
     L.coffee_load_tuning.restype = i32
     L.coffee_set_launch_options.argtypes = [i32]
@@ -452,6 +461,74 @@ def coffee_assemble_batch_packed(segments, seg_of: torch.Tensor, cell_of: torch.
                                            workspace.data_ptr(), workspace.numel(), _stream(stream))
     _check(st, "coffee_assemble_batch_packed")
     return out, out_offset
+
+
+def coffee_csr_pattern(cell_to_dof: torch.Tensor, ndofs: int, ncomp: int = 1, stream=None):
+    """CSR pattern (row_ptr int64 [ndofs * ncomp + 1], col_idx int32 [nnz]) of
+    the global matrix of the space with this cell-to-dof map."""
+    _need(cell_to_dof, "cell_to_dof", torch.int32)
+    if cell_to_dof.ndim != 2:
+        raise ValueError(f"cell_to_dof has shape {tuple(cell_to_dof.shape)}, expected (ncells, nloc)")
+    ncells, nloc = cell_to_dof.shape
+    dev = cell_to_dof.device
+    wsb = int(_lib.coffee_csr_pattern_workspace_size(ncells, nloc, ndofs))
+    if wsb < 0:
+        raise CoffeeError(1, "coffee_csr_pattern_workspace_size")
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    row_ptr = torch.empty(ndofs * ncomp + 1, dtype=torch.int64, device=dev)
+    nnz = C.c_int64()
+    args = [_dptr(cell_to_dof, torch.int32, "cell_to_dof"), ncells, nloc, ndofs, ncomp,
+            _dptr(row_ptr, torch.int64, "row_ptr")]
+    st = _lib.coffee_csr_pattern(*args, None, 0, C.byref(nnz), ws.data_ptr(), ws.numel(), _stream(stream))
+    if st not in (0, 3):
+        _check(st, "coffee_csr_pattern")
+    col_idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+    st = _lib.coffee_csr_pattern(*args, col_idx.data_ptr(), col_idx.numel(), C.byref(nnz), ws.data_ptr(),
+                                 ws.numel(), _stream(stream))
+    _check(st, "coffee_csr_pattern")
+    return row_ptr, col_idx[:nnz.value]
+
+
+def coffee_assemble_csr(form, cell, degree: int, coords, cell_to_vertex, row_ptr, col_idx, ndofs: int,
+                        cell_to_dof=None, coeffs=(), constants=(), quad_degree: int = -1, precision: str = "fp64",
+                        values=None, workspace=None, stream=None) -> torch.Tensor:
+    """Values of the global matrix in the CSR pattern (coffee_assemble_csr)."""
+    c = CELLS[cell]
+    _check_mesh(c, coords, cell_to_vertex)
+    ncells = cell_to_vertex.shape[0]
+    _check_fields(coeffs, c, ncells)
+    nloc = _nloc(c, degree)
+    N = _tensor_dim(FORMS[form], c, degree)
+    if N <= 0:
+        raise ValueError(f"{form} has no element matrix")
+    ncomp = N // nloc
+    if cell_to_dof is not None:
+        _need(cell_to_dof, "cell_to_dof", torch.int32, shape=(ncells, nloc))
+    elif degree != 1:
+        raise ValueError("cell_to_dof is required above degree 1")
+    _need(row_ptr, "row_ptr", torch.int64, shape=(ndofs * ncomp + 1,))
+    _need(col_idx, "col_idx", torch.int32)
+    nnz = col_idx.numel()
+    odt = torch.float64 if precision == "fp64" else torch.float32
+    if values is None:
+        values = torch.empty(nnz, dtype=odt, device=coords.device)
+    _need(values, "values", odt, numel=nnz)
+    wsb = int(_lib.coffee_assemble_csr_workspace_size(FORMS[form], c, degree, PRECISIONS[precision], ncells))
+    if workspace is None:
+        workspace = torch.empty(max(wsb, 16), dtype=torch.uint8, device=coords.device)
+    if workspace.numel() < wsb:
+        raise ValueError(f"workspace has {workspace.numel()} bytes, expected at least {wsb}")
+    cst = np.ascontiguousarray(constants, dtype=np.float64)
+    st = _lib.coffee_assemble_csr(FORMS[form], c, degree, quad_degree, PRECISIONS[precision],
+                                  _dptr(coords, torch.float64, "coords"), coords.shape[0],
+                                  _dptr(cell_to_vertex, torch.int32, "cell_to_vertex"), ncells,
+                                  _fields(list(coeffs)), len(coeffs), cst.ctypes.data if cst.size else None, cst.size,
+                                  _dptr(cell_to_dof, torch.int32, "cell_to_dof", allow_none=True), ndofs,
+                                  _dptr(row_ptr, torch.int64, "row_ptr"), _dptr(col_idx, torch.int32, "col_idx"), nnz,
+                                  _dptr(values, odt, "values"), workspace.data_ptr(), workspace.numel(),
+                                  _stream(stream))
+    _check(st, "coffee_assemble_csr")
+    return values
 
 
 NOALLOC_MAX_ENTRIES = 4194304  # COFFEE_NOALLOC_MAX_ENTRIES

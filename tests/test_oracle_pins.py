@@ -514,3 +514,52 @@ def test_svk_residual_is_energy_gradient(oracle):
         lam = np.zeros((2, 3 * n)); lam[:, i] = 1.0
         _, _, gr = oracle.adjoint("svk_residual", mesh, 2, lam=lam, **kw)
         assert rel(np.transpose(gr[0], (0, 2, 1)).reshape(2, -1), Jm[:, i, :]) < 1e-12
+
+
+# ---------------------------------------------------------------- global assembly
+
+@pytest.mark.parametrize("n", [3, 6])
+def test_global_p1_stiffness_is_five_point_stencil(oracle, n):
+    """On the unjittered split square, the global P1 stiffness matrix (the
+    Helmholtz matrix minus the mass matrix, f = 1) has the interior rows of the
+    5-point finite-difference Laplacian: 4 on the diagonal, -1 for the four
+    axis neighbours, 0 for the two diagonal neighbours in the pattern."""
+    mesh = I.make_mesh(2, n, 0.0, np.random.default_rng(0))
+    V = mesh.nvert
+    K = (oracle.assemble_global("helmholtz", mesh, 1, mesh.cells, V)
+         - oracle.assemble_global("mass", mesh, 1, mesh.cells, V)).toarray()
+    m = n + 1
+    for j in range(1, n):
+        for i in range(1, n):
+            v = i + m * j
+            row = np.zeros(V)
+            row[v] = 4
+            for w in (v - 1, v + 1, v - m, v + m):
+                row[w] = -1
+            np.testing.assert_allclose(K[v], row, atol=1e-13)
+
+
+@pytest.mark.parametrize("d,n,p", [(2, 4, 1), (2, 3, 2), (3, 2, 1), (3, 2, 2)])
+def test_global_mass_totals_and_symmetry(oracle, d, n, p):
+    """Global mass (f = 1) on a jittered mesh: all entries sum to the domain's
+    measure 1, the matrix is symmetric; the global stiffness rows sum to 0."""
+    mesh = I.make_mesh(d, n, 0.15, np.random.default_rng(3))
+    if p == 1:
+        c2d, nd = mesh.cells, mesh.nvert
+    else:
+        c2d, nd = I.p2_dofmap(mesh.cells, mesh.n, d)
+    M = oracle.assemble_global("mass", mesh, p, c2d, nd)
+    H = oracle.assemble_global("helmholtz", mesh, p, c2d, nd)
+    assert abs(M.sum() - 1.0) < 1e-13
+    assert abs(M - M.T).max() < 1e-15
+    K = (H - M).toarray()
+    assert np.max(np.abs(K.sum(axis=1))) < 1e-12 * np.max(np.abs(K))
+
+
+def test_global_p1_pattern_count(oracle):
+    """The P1 pattern of the n x n split square has V + 2 * edges nonzeros:
+    (n+1)^2 + 2 (3 n^2 + 2 n)."""
+    for n in (2, 5):
+        mesh = I.make_mesh(2, n, 0.1, np.random.default_rng(1))
+        M = oracle.assemble_global("mass", mesh, 1, mesh.cells, mesh.nvert)
+        assert M.nnz == (n + 1) ** 2 + 2 * (3 * n * n + 2 * n)
