@@ -325,13 +325,25 @@ const char* coffee_status_string(int status);
  * thread-safe with concurrent assembly calls. */
 void coffee_set_launch_options(int grid_mult);
 
+/* Tile-shape variant of the symmetric engine (mass, Helmholtz) used by
+ * subsequent coffee_assemble calls in this process, for the autotuner: 0
+ * keeps the reference fragments in registers, 1 stages them in LDS with the
+ * register budget of two waves per SIMD, 2 reads them through the caches with
+ * that budget; -1 (the default) takes the tuning cache's choice, else 0. A
+ * key compiled without the requested variant runs variant 0
+ * (coffee_has_variant tells which keys have them). Not thread-safe with
+ * concurrent assembly calls. */
+void coffee_set_variant(int variant);
+int coffee_has_variant(int form, int cell, int degree, int field_degree, int precision, int variant);
+
 /* Loads a tuning cache written by the autotuner (paper_1407_0904_amd/tuner.py):
  * per (form, cell, degree, field degree, precision) grid multipliers for
  * coffee_assemble, and per batch bin type the store variant and task size
  * (used when a segment's task_cells is 0). Without this call the file named by
  * the environment variable COFFEE_TUNE_CACHE is loaded on first use. NULL
  * clears the cache. Text format: lines "linear form cell degree fd prec
- * grid_mult" and "batch form cell degree prec variant task_cells ns_per_cell".
+ * grid_mult [variant]", "batch form cell degree prec variant task_cells
+ * ns_per_cell" and "packed form cell degree prec task_cells ns_per_cell".
  * Errors: COFFEE_E_INVALID_ARG (unreadable file or malformed line; the
  * previous cache is kept). */
 coffee_status coffee_load_tuning(const char* path);

@@ -83,6 +83,10 @@ def _load():
     L.coffee_load_tuning.restype = i32
     L.coffee_set_launch_options.argtypes = [i32]
     L.coffee_set_launch_options.restype = None
+    L.coffee_set_variant.argtypes = [i32]
+    L.coffee_set_variant.restype = None
+    L.coffee_has_variant.argtypes = [i32, i32, i32, i32, i32, i32]
+    L.coffee_has_variant.restype = i32
     return L
 
 
@@ -572,6 +576,15 @@ def coffee_check_geometry(cell, coords, cell_to_vertex, stream=None) -> int:
 
 def coffee_set_launch_options(grid_mult: int = 0):
     _lib.coffee_set_launch_options(int(grid_mult))
+
+
+def coffee_set_variant(variant: int = -1):
+    _lib.coffee_set_variant(int(variant))
+
+
+def coffee_has_variant(form, cell, degree: int, field_degree: int, precision: str, variant: int) -> bool:
+    return bool(_lib.coffee_has_variant(FORMS[form], CELLS[cell], degree, field_degree, PRECISIONS[precision],
+                                        variant))
 
 
 def coffee_load_tuning(path: str | None):

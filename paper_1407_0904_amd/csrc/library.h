@@ -34,7 +34,7 @@ coffee_status get_rtable_public(int dev, int form, int dim, int p, int q, int fd
 bool rtable_bytes(int form, int dim, int p, int q, int fd, int prec, std::vector<char>& buf);
 bool r64_table(int form, int dim, int p, int q, int fd, std::vector<double>& h);
 int batch_grid_mult();
-int tuned_grid_mult(int form, int cell, int degree, int fd, int prec);
+int tuned_linear(int form, int cell, int degree, int fd, int prec, int* variant);
 bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* task_cells);
 bool tuned_packed(int form, int cell, int degree, int prec, int* task_cells);
 void free_svk_tables();

@@ -30,14 +30,25 @@ static std::vector<LinEntry>& lin_registry() {
         register_helmholtz_tet(reg);
         register_elasticity(reg);
         register_burgers(reg);
+        register_variants(reg);
     });
     return reg;
 }
 
-const LinEntry* find_linear(int form, int dim, int p, int fd, int prec) {
+// The instance of a key with the given tile-shape variant, or variant 0.
+const LinEntry* find_linear(int form, int dim, int p, int fd, int prec, int variant) {
+    const LinEntry* base = nullptr;
     for (const LinEntry& e : lin_registry())
-        if (e.form == form && e.dim == dim && e.p == p && e.fd == fd && e.prec == prec) return &e;
-    return nullptr;
+        if (e.form == form && e.dim == dim && e.p == p && e.fd == fd && e.prec == prec) {
+            if (e.variant == variant) return &e;
+            if (e.variant == 0) base = &e;
+        }
+    return base;
+}
+
+extern "C" int coffee_has_variant(int form, int cell, int degree, int field_degree, int precision, int variant) {
+    const LinEntry* e = find_linear(form, cell, degree, field_degree, precision, variant);
+    return e && e->variant == variant ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- device table cache
@@ -201,6 +212,7 @@ int num_cu(int dev) {
 // rounded to a multiple of 8 (XCD count); mult <= 0 selects the engine's
 // default (1: both engines are persistent, one resident set of workgroups).
 static int t_grid_mult = 0;
+static int t_variant = -1;  // forced tile-shape variant (-1: tuned or 0)
 
 int batch_grid_mult() { return t_grid_mult; }
 
@@ -218,6 +230,8 @@ int grid_for(int dev, const void* kernel, int threads, int lds_bytes, int64_t nc
 using namespace coffee;
 
 extern "C" void coffee_set_launch_options(int grid_mult) { t_grid_mult = grid_mult; }
+
+extern "C" void coffee_set_variant(int variant) { t_variant = variant; }
 
 extern "C" const char* coffee_status_string(int s) {
     switch (s) {
@@ -310,7 +324,9 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     // degree 1 mass / Helmholtz: thread-per-cell FMA kernel (p1.hip)
     if ((form == COFFEE_MASS || form == COFFEE_HELMHOLTZ) && degree == 1 && fd <= 1 && precision != COFFEE_BF16X3)
         return assemble_p1(form, cell, fd, q, precision, coords, c2v, ncells, coeffs, ncoeff, out, hip_stream);
-    const LinEntry* e = find_linear(form, cell, degree, fd, precision);
+    int tuned_variant = 0;
+    const int tuned = tuned_linear(form, cell, degree, fd, precision, &tuned_variant);
+    const LinEntry* e = find_linear(form, cell, degree, fd, precision, t_variant >= 0 ? t_variant : tuned_variant);
     if (!e) return COFFEE_E_UNSUPPORTED;
     if (ncells == 0) return COFFEE_OK;
     int dev = 0;
@@ -335,7 +351,6 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     a.rfrag = rf;
     a.out = out;
     a.nchunks = (ncells + e->cells_per_chunk - 1) / e->cells_per_chunk;
-    const int tuned = tuned_grid_mult(form, cell, degree, fd, precision);
     const int grid = grid_for(dev, e->kernel, e->threads, e->lds_bytes, a.nchunks, tuned > 0 ? tuned : 1);
     if (e->launch(a, (hipStream_t)hip_stream, grid) != hipSuccess) return COFFEE_E_HIP;
     return COFFEE_OK;

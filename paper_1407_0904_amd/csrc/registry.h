@@ -15,6 +15,7 @@ typedef hipError_t (*LinLaunch)(const dev::LinArgs&, hipStream_t, int grid);
 
 struct LinEntry {
     int form, dim, p, fd, prec;
+    int variant;          // tile-shape variant of the engine (scalar.hpp)
     LinLaunch launch;
     const void* kernel;
     int threads;          // workgroup size
@@ -26,20 +27,20 @@ struct LinEntry {
 // engine (scalar.hpp); the vector forms use the panel engine (vector.hpp).
 constexpr bool uses_scalar_engine(int form) { return form == dev::F_MASS || form == dev::F_HELM; }
 
-template <int FORM, int D, int P, int FD, int PREC>
+template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 const void* kernel_of() {
     if constexpr (uses_scalar_engine(FORM))
-        return reinterpret_cast<const void*>(&dev::k_scalar<FORM, D, P, FD, PREC>);
+        return reinterpret_cast<const void*>(&dev::k_scalar<FORM, D, P, FD, PREC, VAR>);
     else
         return reinterpret_cast<const void*>(&dev::k_vector<FORM, D, P, FD, PREC>);
 }
 
 // The vector engine takes its LDS dynamically (it can exceed the 64 KiB of
 // static allocations); the attribute is set once per kernel.
-template <int FORM, int D, int P, int FD, int PREC>
+template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 hipError_t launch_linear(const dev::LinArgs& a, hipStream_t s, int grid) {
     if constexpr (uses_scalar_engine(FORM)) {
-        hipLaunchKernelGGL((dev::k_scalar<FORM, D, P, FD, PREC>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((dev::k_scalar<FORM, D, P, FD, PREC, VAR>), dim3(grid), dim3(256), 0, s, a);
     } else {
         using C = dev::VecCfg<FORM, D, P, FD, PREC>;
         static const hipError_t attr = hipFuncSetAttribute(
@@ -52,14 +53,14 @@ hipError_t launch_linear(const dev::LinArgs& a, hipStream_t s, int grid) {
     return hipGetLastError();
 }
 
-template <int FORM, int D, int P, int FD, int PREC>
+template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 LinEntry lin_entry() {
     if constexpr (uses_scalar_engine(FORM)) {
-        return LinEntry{FORM, D, P, FD, PREC, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>(),
-                        256, 0, 256};
+        return LinEntry{FORM, D, P, FD, PREC, VAR, &launch_linear<FORM, D, P, FD, PREC, VAR>,
+                        kernel_of<FORM, D, P, FD, PREC, VAR>(), 256, 0, 256};
     } else {
         using C = dev::VecCfg<FORM, D, P, FD, PREC>;
-        return LinEntry{FORM, D, P, FD, PREC, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>(),
+        return LinEntry{FORM, D, P, FD, PREC, 0, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>(),
                         C::WAVES * 64, C::LDS_BYTES, C::WAVES * 16};
     }
 }
@@ -72,11 +73,24 @@ void add_all_prec(std::vector<LinEntry>& v) {
     v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_BF16X3>());
 }
 
+// the symmetric engine's other tile-shape variants (1, 2) for each precision
+template <int FORM, int D, int P, int FD>
+void add_variants(std::vector<LinEntry>& v) {
+    static_assert(uses_scalar_engine(FORM), "tile-shape variants of the symmetric engine");
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F64, 1>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F32, 1>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_BF16X3, 1>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F64, 2>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F32, 2>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_BF16X3, 2>());
+}
+
 void register_mass_tri(std::vector<LinEntry>& v);
 void register_mass_tet(std::vector<LinEntry>& v);
 void register_helmholtz_tri(std::vector<LinEntry>& v);
 void register_helmholtz_tet(std::vector<LinEntry>& v);
 void register_elasticity(std::vector<LinEntry>& v);
 void register_burgers(std::vector<LinEntry>& v);
+void register_variants(std::vector<LinEntry>& v);
 
 }  // namespace coffee

@@ -32,7 +32,17 @@ struct StageCfg {
     static constexpr int STAGE_ELEMS = STAGE ? 8 * NN : 1;
 };
 
-template <int FORM, int D, int P, int FD, int PREC>
+// Tile-shape variants of the symmetric engine, chosen per (form, cell,
+// degree, field degree, precision) by the offline autotuner:
+//   0  reference fragments held in registers when they fit (else read through
+//      the L1/L2 caches), register budget of one wave per SIMD;
+//   1  reference fragments staged in LDS once per workgroup, register budget
+//      of two waves per SIMD;
+//   2  reference fragments read through the L1/L2 caches at every use,
+//      register budget of two waves per SIMD.
+constexpr int kScalarVariants = 3;
+
+template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 struct ScalarCfg {
     using g_t = typename PrecT<PREC>::gtype;
     using frag_t = typename PrecT<PREC>::frag;
@@ -48,18 +58,20 @@ struct ScalarCfg {
     static constexpr bool STAGE = StageCfg<D, P, PREC>::STAGE;
     static constexpr int SE = StageCfg<D, P, PREC>::STAGE_ELEMS;
     static constexpr int REGB = NT * KS * (PREC == PREC_F64 ? 2 : (PREC == PREC_F32 ? 1 : 4));
-    static constexpr bool RREG = REGB <= 64;
+    static constexpr bool RREG = VAR == 0 && REGB <= 64;
+    static constexpr bool RLDS = VAR == 1;
+    static constexpr int NFRAG = NT * KS;  // reference fragments of 64 lanes
     // the staged path writes whole cells, so it needs every n-tile at once
     static constexpr int NTC = STAGE ? NT : (NT < 8 ? NT : 8);
 };
 
 // Per-lane state of the symmetric engine.
-template <int FORM, int D, int P, int FD, int PREC>
+template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 struct ScalarWave {
-    using C = ScalarCfg<FORM, D, P, FD, PREC>;
+    using C = ScalarCfg<FORM, D, P, FD, PREC, VAR>;
     typename C::g_t* gtile;
     typename C::out_t* stage;
-    const typename C::frag_t* rf;
+    const typename C::frag_t* rf;  // global fragments, or the LDS copy (variant 1)
     typename C::out_t* out;
     int lane, col;
     int ua[C::NT], ub[C::NT];
@@ -68,10 +80,10 @@ struct ScalarWave {
 
 // Accumulate n-tiles t0 .. t0 + NTC - 1 of the 16-cell tile whose G rows are
 // in W.gtile.
-template <int FORM, int D, int P, int FD, int PREC, int NTC>
-__device__ inline void scalar_contract(const ScalarWave<FORM, D, P, FD, PREC>& W, int t0,
+template <int FORM, int D, int P, int FD, int PREC, int NTC, int VAR>
+__device__ inline void scalar_contract(const ScalarWave<FORM, D, P, FD, PREC, VAR>& W, int t0,
                                        typename PrecT<PREC>::acc (&acc)[NTC]) {
-    using C = ScalarCfg<FORM, D, P, FD, PREC>;
+    using C = ScalarCfg<FORM, D, P, FD, PREC, VAR>;
 #pragma unroll
     for (int t = 0; t < NTC; ++t) acc[t] = typename C::acc_t{0, 0, 0, 0};
 #pragma unroll
@@ -82,6 +94,7 @@ __device__ inline void scalar_contract(const ScalarWave<FORM, D, P, FD, PREC>& W
             if (t0 + t < C::NT) {
                 typename C::frag_t bf;
                 if constexpr (C::RREG) bf = W.rreg[t0 + t < C::NT ? t0 + t : 0][s];
+                else if constexpr (C::RLDS) bf = as_lds(W.rf)[((t0 + t) * C::KS + s) * 64 + W.lane];
                 else bf = gload(W.rf + ((t0 + t) * C::KS + s) * 64 + W.lane);
                 acc[t] = mfma<PREC>(a, bf, acc[t]);
             }
@@ -93,10 +106,10 @@ __device__ inline void scalar_contract(const ScalarWave<FORM, D, P, FD, PREC>& W
 // is straight-line with compile-time store counts (the compiler can then track
 // outstanding memory operations exactly instead of draining the store queue
 // before the next use of a prefetched load).
-template <int FORM, int D, int P, int FD, int PREC, bool FULL>
-__device__ inline void scalar_tile(const LinArgs& A, ScalarWave<FORM, D, P, FD, PREC>& W, const double* Gv,
+template <int FORM, int D, int P, int FD, int PREC, bool FULL, int VAR = 0>
+__device__ inline void scalar_tile(const LinArgs& A, ScalarWave<FORM, D, P, FD, PREC, VAR>& W, const double* Gv,
                                    int j, int64_t tile_base) {
-    using C = ScalarCfg<FORM, D, P, FD, PREC>;
+    using C = ScalarCfg<FORM, D, P, FD, PREC, VAR>;
     using acc_t = typename C::acc_t;
     using frag_t = typename C::frag_t;
     using out_t = typename C::out_t;
@@ -107,7 +120,7 @@ __device__ inline void scalar_tile(const LinArgs& A, ScalarWave<FORM, D, P, FD, 
 #pragma unroll
     for (int t0 = 0; t0 < NT; t0 += NTC) {
         acc_t acc[NTC];
-        scalar_contract<FORM, D, P, FD, PREC, NTC>(W, t0, acc);
+        scalar_contract<FORM, D, P, FD, PREC, NTC, VAR>(W, t0, acc);
         if constexpr (C::STAGE) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -195,23 +208,29 @@ __device__ inline void G_from_raw(const CellRaw<FORM, D, FD>& raw, const LinArgs
     }
 }
 
-#ifndef COFFEE_SCALAR_WAVES_PER_EU
-#define COFFEE_SCALAR_WAVES_PER_EU 1
-#endif
-template <int FORM, int D, int P, int FD, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(COFFEE_SCALAR_WAVES_PER_EU)))
+constexpr int scalar_waves_per_eu(int var) { return var == 0 ? 1 : 2; }
+
+template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scalar_waves_per_eu(VAR))))
 void k_scalar(LinArgs A) {
-    using C = ScalarCfg<FORM, D, P, FD, PREC>;
+    using C = ScalarCfg<FORM, D, P, FD, PREC, VAR>;
     constexpr int KR = C::KR, NT = C::NT, KS = C::KS, NS = C::NS;
     __shared__ __attribute__((aligned(16))) typename C::g_t sG[4][16 * C::ROW];
     __shared__ __attribute__((aligned(16))) typename C::out_t sO[4][C::SE];
+    __shared__ __attribute__((aligned(16))) typename C::frag_t sR[C::RLDS ? C::NFRAG * 64 : 1];
     const int wave = threadIdx.x >> 6;
-    ScalarWave<FORM, D, P, FD, PREC> W;
+    ScalarWave<FORM, D, P, FD, PREC, VAR> W;
     W.lane = threadIdx.x & 63;
     W.col = W.lane & 15;
     W.gtile = sG[wave];
     W.stage = sO[wave];
     W.rf = reinterpret_cast<const typename C::frag_t*>(A.rfrag);
+    if constexpr (C::RLDS) {
+        // variant 1: the workgroup copies the reference fragments to LDS once
+        for (int i = threadIdx.x; i < C::NFRAG * 64; i += blockDim.x) sR[i] = gload(W.rf + i);
+        __syncthreads();
+        W.rf = sR;
+    }
     W.out = reinterpret_cast<typename C::out_t*>(A.out);
     const int lane = W.lane;
 
@@ -276,10 +295,10 @@ void k_scalar(LinArgs A) {
         const int64_t n2 = next + GS < nfull ? next + GS : chunk;
         load_raw<FORM, D, FD>(A, cell_of(n1), ix, raw);
         load_idx<FORM, D, FD>(A, cell_of(n2), ix);
-        scalar_tile<FORM, D, P, FD, PREC, true>(A, W, Gv, 0, wave_base);
-        scalar_tile<FORM, D, P, FD, PREC, true>(A, W, Gv, 1, wave_base + 16);
-        scalar_tile<FORM, D, P, FD, PREC, true>(A, W, Gv, 2, wave_base + 32);
-        scalar_tile<FORM, D, P, FD, PREC, true>(A, W, Gv, 3, wave_base + 48);
+        scalar_tile<FORM, D, P, FD, PREC, true, VAR>(A, W, Gv, 0, wave_base);
+        scalar_tile<FORM, D, P, FD, PREC, true, VAR>(A, W, Gv, 1, wave_base + 16);
+        scalar_tile<FORM, D, P, FD, PREC, true, VAR>(A, W, Gv, 2, wave_base + 32);
+        scalar_tile<FORM, D, P, FD, PREC, true, VAR>(A, W, Gv, 3, wave_base + 48);
         G_from_raw<FORM, D, FD>(raw, A, true, Gv);
         chunk = next;
     }
@@ -300,7 +319,7 @@ void k_scalar(LinArgs A) {
         for (int j = 0; j < 4; ++j) {
             const int64_t tile_base = wave_base + 16 * j;
             if (tile_base >= A.ncells) break;  // wave-uniform
-            scalar_tile<FORM, D, P, FD, PREC, false>(A, W, Gv, j, tile_base);
+            scalar_tile<FORM, D, P, FD, PREC, false, VAR>(A, W, Gv, j, tile_base);
         }
     }
 }

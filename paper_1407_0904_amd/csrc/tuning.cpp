@@ -1,7 +1,7 @@
 // Tuning cache of libcoffee: launch choices measured by the autotuner
 // (paper_1407_0904_amd/tuner.py), one entry per line of a text file:
 //
-//   linear <form> <cell> <degree> <field_degree> <precision> <grid_mult>
+//   linear <form> <cell> <degree> <field_degree> <precision> <grid_mult> [<variant>]
 //   batch  <form> <cell> <degree> <precision> <variant> <task_cells> <ns_per_cell>
 //   packed <form> <cell> <degree> <precision> <task_cells> <ns_per_cell>
 //
@@ -18,6 +18,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
 
 #include "../../include/coffee.h"
 
@@ -30,14 +31,14 @@ struct BatchTune {
 
 static std::mutex g_tmu;
 static bool g_loaded = false;
-static std::map<std::tuple<int, int, int, int, int>, int> g_linear;      // -> grid_mult
+static std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_linear;  // -> (grid_mult, variant)
 static std::map<std::tuple<int, int, int, int>, BatchTune> g_batch;       // (form, cell, degree, prec)
 static std::map<std::tuple<int, int, int, int>, BatchTune> g_packed;      // (form, cell, degree, prec)
 
 static coffee_status parse(const char* path) {
     FILE* f = std::fopen(path, "r");
     if (!f) return COFFEE_E_INVALID_ARG;
-    std::map<std::tuple<int, int, int, int, int>, int> lin;
+    std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> lin;
     std::map<std::tuple<int, int, int, int>, BatchTune> bat, pk;
     char line[512];
     coffee_status st = COFFEE_OK;
@@ -47,12 +48,13 @@ static coffee_status parse(const char* path) {
         char kind[32];
         if (std::sscanf(line, "%31s", kind) != 1) continue;
         if (!std::strcmp(kind, "linear")) {
-            int form, cell, deg, fd, prec, gm;
-            if (std::sscanf(line, "%*s %d %d %d %d %d %d", &form, &cell, &deg, &fd, &prec, &gm) != 6 || gm < 1) {
+            int form, cell, deg, fd, prec, gm, var = 0;
+            const int nf = std::sscanf(line, "%*s %d %d %d %d %d %d %d", &form, &cell, &deg, &fd, &prec, &gm, &var);
+            if (nf < 6 || gm < 1 || var < 0 || var > 2) {
                 st = COFFEE_E_INVALID_ARG;
                 break;
             }
-            lin[std::make_tuple(form, cell, deg, fd, prec)] = gm;
+            lin[std::make_tuple(form, cell, deg, fd, prec)] = std::make_pair(gm, var);
         } else if (!std::strcmp(kind, "batch")) {
             int form, cell, deg, prec, var, tc;
             double ns;
@@ -100,11 +102,12 @@ static void ensure_loaded() {
     if (env && *env) (void)parse(env);
 }
 
-int tuned_grid_mult(int form, int cell, int degree, int fd, int prec) {
+int tuned_linear(int form, int cell, int degree, int fd, int prec, int* variant) {
     std::lock_guard<std::mutex> lk(g_tmu);
     ensure_loaded();
     auto it = g_linear.find(std::make_tuple(form, cell, degree, fd, prec));
-    return it == g_linear.end() ? 0 : it->second;
+    *variant = it == g_linear.end() ? 0 : it->second.second;
+    return it == g_linear.end() ? 0 : it->second.first;
 }
 
 bool tuned_batch(int form, int cell, int degree, int prec, int* variant, int* task_cells) {

@@ -6,7 +6,10 @@ reports the best over every feasible unroll factor for its register tiling
 (section 5.6); the search runs offline, so its cost never reaches the assembly
 call. Keys and candidates:
 
-* coffee_assemble (form, cell, degree, field degree, precision): the grid
+* coffee_assemble (form, cell, degree, field degree, precision): the
+  tile-shape variant of the symmetric engine (reference fragments in
+  registers at one wave per SIMD, in LDS at two waves per SIMD, or read
+  through the caches at two waves per SIMD; coffee_set_variant) x the grid
   multiplier (persistent grid of CUs x resident workgroups x m, or one
   workgroup per 256 cells);
 * mixed-batch bins (form, cell, degree, precision): store variant (LDS-staged
@@ -49,8 +52,9 @@ def _time(fn, reps: int = 7, warm: int = 2) -> float:
     return statistics.median(ts)
 
 
-def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4, 8, 64), log=print):
-    """Best grid multiplier per precision for one named workload."""
+def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4, 8, 64), variants=(0, 1, 2),
+                log=print):
+    """Best (tile-shape variant, grid multiplier) per precision for one named workload."""
     import torch
     from . import coffee, inputs
     dev = torch.device("cuda:0")
@@ -64,16 +68,22 @@ def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4
         out = torch.empty(coffee.output_shape(w.form, w.mesh.ncells, w.mesh.d, w.degree),
                           dtype=torch.float64 if prec == "fp64" else torch.float32, device=dev)
         best = None
-        for m in candidates:
-            coffee.coffee_set_launch_options(m)
-            ms = _time(lambda: coffee.coffee_assemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields,
-                                                      constants=w.constants, quad_degree=w.quad_degree,
-                                                      precision=prec, out=out))
-            log(f"  {workload_name} {prec} grid_mult {m}: {ms * 1e3:.1f} us")
-            if best is None or ms < best[1]:
-                best = (m, ms)
+        for var in variants:
+            if var and not coffee.coffee_has_variant(w.form, w.mesh.d, w.degree, fd, prec, var):
+                continue
+            coffee.coffee_set_variant(var)
+            for m in candidates:
+                coffee.coffee_set_launch_options(m)
+                call = coffee.PreparedAssemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields,
+                                               constants=w.constants, quad_degree=w.quad_degree, precision=prec,
+                                               out=out)
+                ms = _time(call)
+                log(f"  {workload_name} {prec} variant {var} grid_mult {m}: {ms * 1e3:.1f} us")
+                if best is None or ms < best[2]:
+                    best = (var, m, ms)
         coffee.coffee_set_launch_options(0)
-        entries.append(("linear", FORM_IDS[w.form], w.mesh.d, w.degree, fd, PREC_IDS[prec], best[0]))
+        coffee.coffee_set_variant(-1)
+        entries.append(("linear", FORM_IDS[w.form], w.mesh.d, w.degree, fd, PREC_IDS[prec], best[1], best[0]))
         del out
     return entries
 
@@ -162,7 +172,7 @@ def write_cache(path: str, entries, header: str = ""):
             f.write(f"# {header}\n")
         for e in entries:
             if e[0] == "linear":
-                f.write("linear %d %d %d %d %d %d\n" % e[1:])
+                f.write("linear %d %d %d %d %d %d %d\n" % e[1:])
             elif e[0] == "packed":
                 f.write("packed %d %d %d %d %d %.6f\n" % e[1:])
             else:
@@ -197,6 +207,8 @@ def main(argv=None):
     if not args.quick:
         entries += tune_linear("helmholtz_p2_tet", ("fp64", "fp32", "bf16x3"))
         entries += tune_linear("helmholtz_p1_tri", ("fp64",))
+        entries += tune_linear("elasticity_p2_tet", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 4, 8))
+        entries += tune_linear("burgers_p2_tet", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 4, 8))
         mb = inputs.mixed_batch()
     else:
         mb = inputs.mixed_batch(n_tri=64, n_tet=12, tri_counts=(3000, 2000, 1500, 1000),

@@ -308,3 +308,29 @@ def test_prepared_assemble_equals_assemble(cf):
         out = call()
         torch.cuda.synchronize()
         assert torch.equal(out, ref)
+
+
+VARIANT_KEYS = [("helmholtz", 3, 2, 2), ("helmholtz", 3, 2, 1), ("mass", 3, 2, 2), ("mass", 3, 2, 1),
+                ("helmholtz", 2, 3, 1), ("helmholtz", 2, 4, 1)]
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("form,d,p,fd", VARIANT_KEYS)
+def test_tile_shape_variants(cf, oracle, form, d, p, fd, prec, variant):
+    """Every tile-shape variant the autotuner can choose (reference fragments
+    in registers, in LDS, or through the caches) against the oracle, on a mesh
+    of several 256-cell chunks with a ragged tail."""
+    from gpu_util import TOL, assemble_gpu, cell_rel_err
+    assert variant == 0 or cf.coffee_has_variant(form, d, p, fd, prec, variant)
+    rng = np.random.default_rng(500 + 10 * p + fd)
+    mesh = I.make_mesh(d, 14 if d == 2 else 5, 0.15, rng)  # 392 / 750 cells
+    fields = [_field_of_degree(mesh, fd, rng)]
+    ref = oracle.assemble(form, mesh, p, fields=fields)
+    cf.coffee_set_variant(variant)
+    try:
+        got = assemble_gpu(form, mesh, p, fields, precision=prec).cpu().numpy()
+    finally:
+        cf.coffee_set_variant(-1)
+    err = cell_rel_err(got, ref)
+    assert err < TOL[prec], err
