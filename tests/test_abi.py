@@ -96,10 +96,13 @@ def test_tuning_cache_parsing(lib, tmp_path):
     f = lib.coffee_load_tuning
     f.argtypes = [C.c_char_p]
     good = tmp_path / "good.txt"
-    good.write_text("# comment\nlinear 1 3 2 2 0 2\nbatch 0 2 1 1 1 128 0.25\npacked 0 2 1 1 512 0.2\n\n")
+    good.write_text("# comment\nlinear 1 3 2 2 0 2\nlinear 1 3 2 2 1 4 1\nbatch 0 2 1 1 1 128 0.25\n"
+                    "packed 0 2 1 1 512 0.2\n\n")
     assert f(str(good).encode()) == 0
     bad = tmp_path / "bad.txt"
     bad.write_text("batch 0 2 1 1 1 100 0.25\n")
+    assert f(str(bad).encode()) == 1
+    bad.write_text("linear 1 3 2 2 0 4 3\n")  # no tile-shape variant 3
     assert f(str(bad).encode()) == 1
     bad.write_text("packed 0 2 1 1 96 0.25\n")
     assert f(str(bad).encode()) == 1
@@ -107,7 +110,7 @@ def test_tuning_cache_parsing(lib, tmp_path):
     assert f(None) == 0
     from paper_1407_0904_amd import tuner
     out = tmp_path / "w.txt"
-    tuner.write_cache(str(out), [("linear", 1, 3, 2, 2, 0, 4), ("batch", 1, 3, 3, 1, 0, 256, 1.5),
+    tuner.write_cache(str(out), [("linear", 1, 3, 2, 2, 0, 4, 1), ("batch", 1, 3, 3, 1, 0, 256, 1.5),
                                  ("packed", 1, 3, 3, 1, 512, 1.25)])
     assert f(str(out).encode()) == 0
     assert tuner.read_batch_costs(str(out)) == {("helmholtz", 3, 3, "fp32"): 1.5}
