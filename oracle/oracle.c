@@ -251,6 +251,7 @@ static int nscalar(int dim, int p) {
 
 int oracle_tabulate(int dim, int degree, int quad_degree, int* nq, int* ndof,
                     double* points, double* weights, double* basis, double* dbasis) {
+    if (dim == OR_PRISM) return prism_tabulate(degree, quad_degree, nq, ndof, points, weights, basis, dbasis);
     if ((dim != 2 && dim != 3) || degree < 0 || degree > MAXP || !nq || !ndof) return OR_E_INVALID_ARG;
     if (quad_degree < 0) return OR_E_INVALID_ARG;
     int alpha[MAXN][4];
@@ -279,6 +280,7 @@ int oracle_tabulate(int dim, int degree, int quad_degree, int* nq, int* ndof,
 /* Basis values phi[npts][ndof] and reference gradients dphi[dim][npts][ndof]
  * of the degree-p element at arbitrary reference points X[npts][dim]. */
 int oracle_basis_at(int dim, int degree, int npts, const double* X, double* phi, double* dphi) {
+    if (dim == OR_PRISM) return prism_basis_at(degree, npts, X, phi, dphi);
     if ((dim != 2 && dim != 3) || degree < 0 || degree > MAXP || npts < 0 || (npts && (!X || !phi)))
         return OR_E_INVALID_ARG;
     int alpha[MAXN][4];
@@ -331,9 +333,11 @@ static int make_table(int dim, int p, int q, table* t) {
 }
 
 int oracle_tensor_dim(int form, int dim, int degree) {
+    if (dim == OR_PRISM)
+        return (form == OR_MASS || form == OR_HELMHOLTZ || form == OR_DIFFUSION) ? prism_ndofs(degree) : -1;
     int n = nscalar(dim, degree);
     switch (form) {
-        case OR_MASS: case OR_HELMHOLTZ: return n;
+        case OR_MASS: case OR_HELMHOLTZ: case OR_DIFFUSION: return n;
         case OR_ELASTICITY: case OR_BURGERS: case OR_SVK_RESIDUAL: case OR_SVK_JACOBIAN: return dim * n;
         case OR_SVK_ENERGY: return 0;
         default: return -1;
@@ -349,7 +353,7 @@ static int make_ctx(int form, int dim, int degree, int quad_degree, const oracle
                     int nfield, const double* constants, int nconst, ctx* c) {
     memset(c, 0, sizeof *c);
     if (dim != 2 && dim != 3) return OR_E_INVALID_ARG;
-    if (form < OR_MASS || form > OR_SVK_JACOBIAN) return OR_E_INVALID_ARG;
+    if (form < OR_MASS || form > OR_DIFFUSION) return OR_E_INVALID_ARG;
     if (degree < 1 || degree > MAXP) return OR_E_UNSUPPORTED;
     if (nfield < 0 || nfield > 4 || (nfield > 0 && !fields) || nconst < 0) return OR_E_INVALID_ARG;
     if (nconst > 0 && !constants) return OR_E_INVALID_ARG;
@@ -357,13 +361,16 @@ static int make_ctx(int form, int dim, int degree, int quad_degree, const oracle
     c->form = form; c->dim = dim; c->p = degree; c->nfield = nfield;
     int N = oracle_tensor_dim(form, dim, degree);
     c->N = N;
-    c->ncomp_space = (form == OR_MASS || form == OR_HELMHOLTZ) ? 1 : dim;
+    c->ncomp_space = (form == OR_MASS || form == OR_HELMHOLTZ || form == OR_DIFFUSION) ? 1 : dim;
     c->out_len = form == OR_SVK_ENERGY ? 1 : (form == OR_SVK_RESIDUAL ? N : N * N);
     /* field count and shape per form */
     int need_vec = 0;
     switch (form) {
         case OR_MASS: case OR_HELMHOLTZ:
             if (nfield > 1) return OR_E_INVALID_ARG;
+            break;
+        case OR_DIFFUSION:
+            if (nfield != 0) return OR_E_INVALID_ARG;
             break;
         case OR_ELASTICITY:
             if (!(nfield == 2 || (nfield == 0 && nconst >= 2))) return OR_E_INVALID_ARG;
@@ -448,6 +455,9 @@ int oracle_assemble(int form, int dim, int degree, int quad_degree,
                     const double* coords, int64_t nvert, const int32_t* c2v, int64_t ncells,
                     const oracle_field* fields, int nfield, const double* constants, int nconst,
                     const int64_t* cells, int64_t nsel, double* out, int nthreads) {
+    if (dim == OR_PRISM)
+        return prism_assemble(form, degree, quad_degree, coords, nvert, c2v, ncells, fields, nfield, constants,
+                              nconst, cells, nsel, out, nthreads);
     int st = check_mesh_args(coords, nvert, c2v, ncells);
     if (st) return st;
     if (!cells && nsel != ncells) return OR_E_INVALID_ARG;

@@ -24,9 +24,15 @@ extern "C" {
 
 enum { OR_OK = 0, OR_E_INVALID_ARG = 1, OR_E_UNSUPPORTED = 2, OR_E_DEGENERATE = 4, OR_E_NOMEM = 6 };
 
-/* Forms (same numbering as the library's public enum). */
+/* Forms (same numbering as the library's public enum). DIFFUSION is the
+ * Helmholtz operator without its mass term, scaled by two constants:
+ * kappa dt grad u . grad v (constants kappa, dt; both 1 if absent). */
 enum { OR_MASS = 0, OR_HELMHOLTZ = 1, OR_ELASTICITY = 2, OR_BURGERS = 3,
-       OR_SVK_ENERGY = 4, OR_SVK_RESIDUAL = 5, OR_SVK_JACOBIAN = 6 };
+       OR_SVK_ENERGY = 4, OR_SVK_RESIDUAL = 5, OR_SVK_JACOBIAN = 6, OR_DIFFUSION = 7 };
+
+/* Cell argument `dim`: 2 triangle, 3 tetrahedron, OR_PRISM the prism
+ * (triangle x interval, six vertices; prism.c). */
+enum { OR_PRISM = 6 };
 
 /* A coefficient field. values: global [ndofs][ncomp] if cell_to_dof is not
  * NULL (cell_to_dof is [ncells][nloc]); else cell-major [ncells][nloc][ncomp].
@@ -85,6 +91,17 @@ int oracle_adjoint(int form, int dim, int degree, int quad_degree,
                    const double* constants, int nconst,
                    const double* lam, const double* u, double seed,
                    double* grad_coords, double* const* grad_fields, double* value,
+                   int nthreads);
+
+/* Prism cells (prism.c), reached through the calls above with dim = OR_PRISM:
+ * mass, Helmholtz and diffusion, degree 1..4, a degree-1 prism field. */
+int prism_ndofs(int p);
+int prism_tabulate(int degree, int quad_degree, int* nq, int* ndof, double* points, double* weights,
+                   double* basis, double* dbasis);
+int prism_basis_at(int degree, int npts, const double* X, double* phi, double* dphi);
+int prism_assemble(int form, int degree, int quad_degree, const double* coords, int64_t nvert,
+                   const int32_t* c2v, int64_t ncells, const oracle_field* fields, int nfield,
+                   const double* constants, int nconst, const int64_t* cells, int64_t nsel, double* out,
                    int nthreads);
 
 #ifdef __cplusplus

@@ -15,12 +15,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
 FORMS = {"mass": 0, "helmholtz": 1, "elasticity": 2, "burgers": 3,
-         "svk_energy": 4, "svk_residual": 5, "svk_jacobian": 6}
+         "svk_energy": 4, "svk_residual": 5, "svk_jacobian": 6, "diffusion": 7}
+PRISM = 6  # cell code of the prism (triangle x interval); simplices use their dimension
 
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc -O2 and OpenMP."""
-    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "symrule.c")]
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "symrule.c", "prism.c")]
     deps = srcs + [os.path.join(_HERE, f) for f in ("element.inc", "oracle.h")]
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(f) for f in deps):
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
@@ -100,12 +101,14 @@ def symmetric_rule(dim: int, q: int):
 
 
 def tabulate(dim: int, degree: int, quad_degree: int):
+    """Rule and basis tables; dim 2, 3 or PRISM (points then have 3 coordinates)."""
     nq, nd = C.c_int(), C.c_int()
     st = lib().oracle_tabulate(dim, degree, quad_degree, C.byref(nq), C.byref(nd), None, None, None, None)
     if st:
         raise OracleError(st)
     q, n = nq.value, nd.value
-    X = np.zeros((q, dim)); W = np.zeros(q); B = np.zeros((q, n)); D = np.zeros((dim, q, n))
+    sd = 3 if dim == PRISM else dim
+    X = np.zeros((q, sd)); W = np.zeros(q); B = np.zeros((q, n)); D = np.zeros((sd, q, n))
     st = lib().oracle_tabulate(dim, degree, quad_degree, C.byref(nq), C.byref(nd), _ptr(X), _ptr(W), _ptr(B), _ptr(D))
     if st:
         raise OracleError(st)
@@ -114,10 +117,14 @@ def tabulate(dim: int, degree: int, quad_degree: int):
 
 def basis_at(dim: int, degree: int, X: np.ndarray):
     """Basis values [npts, n] and reference gradients [dim, npts, n] at points X [npts, dim]."""
-    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, dim)
-    n = (degree + 1) * (degree + 2) // 2 if dim == 2 else (degree + 1) * (degree + 2) * (degree + 3) // 6
+    sd = 3 if dim == PRISM else dim
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, sd)
+    if dim == PRISM:
+        n = (degree + 1) * (degree + 2) // 2 * (degree + 1)
+    else:
+        n = (degree + 1) * (degree + 2) // 2 if dim == 2 else (degree + 1) * (degree + 2) * (degree + 3) // 6
     phi = np.zeros((X.shape[0], n))
-    dphi = np.zeros((dim, X.shape[0], n))
+    dphi = np.zeros((sd, X.shape[0], n))
     st = lib().oracle_basis_at(dim, degree, X.shape[0], _ptr(X), _ptr(phi), _ptr(dphi))
     if st:
         raise OracleError(st)
@@ -141,18 +148,20 @@ def _fields(fields):
 
 def assemble(form: str, mesh, degree: int, quad_degree: int = -1, fields=(), constants=(),
              cells=None, nthreads: int = 0) -> np.ndarray:
-    """Element tensors [nsel, N, N] / [nsel, N] / [nsel] for the selected cells."""
+    """Element tensors [nsel, N, N] / [nsel, N] / [nsel] for the selected cells
+    (simplex or prism meshes: the cell code comes from the connectivity)."""
     coords = np.ascontiguousarray(mesh.coords, dtype=np.float64)
     c2v = np.ascontiguousarray(mesh.cells, dtype=np.int32)
     E = c2v.shape[0]
+    cell = PRISM if c2v.shape[1] == 6 else mesh.d
     sel = None if cells is None else np.ascontiguousarray(cells, dtype=np.int64)
     nsel = E if sel is None else sel.shape[0]
-    N = tensor_dim(form, mesh.d, degree)
+    N = tensor_dim(form, cell, degree)
     shape = (nsel,) if form == "svk_energy" else ((nsel, N) if form == "svk_residual" else (nsel, N, N))
     out = np.zeros(shape)
     farr, keep = _fields(list(fields))
     cst = np.ascontiguousarray(constants, dtype=np.float64)
-    st = lib().oracle_assemble(FORMS[form], mesh.d, degree, quad_degree, _ptr(coords), coords.shape[0],
+    st = lib().oracle_assemble(FORMS[form], cell, degree, quad_degree, _ptr(coords), coords.shape[0],
                                _ptr(c2v), E, farr, len(fields), _ptr(cst) if cst.size else None, cst.size,
                                _ptr(sel), nsel, _ptr(out), nthreads)
     if st:

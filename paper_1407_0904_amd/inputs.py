@@ -16,6 +16,13 @@ available; these stand in for them):
   tetrahedra, one per permutation pi of the axes (lexicographic order): the
   path v000 -> +e_pi0 -> +e_pi1 -> v111. For odd pi the last two vertices
   are swapped so that every tetrahedron is positively oriented.
+* Prisms: the triangle mesh of the unit square extruded through n layers of
+  height h. The prism over base triangle (a, b, c) in layer k has vertices
+  (a,k), (a,k+1), (b,k), (b,k+1), (c,k), (c,k+1) (each base vertex at the
+  bottom, then at the top), and cells run layer-fastest within the column of
+  each base triangle (cell t n + k). Jitter moves interior vertices in all
+  three directions, so the prisms are not affine images of the reference
+  prism (their top and bottom triangles differ and their sides are warped).
 * Vertex index v = i + (n+1) j (+ (n+1)^2 k).
 * Jitter: every coordinate of every interior vertex moves by an independent
   draw from U[-r h, r h] (h = 1/n); boundary vertices do not move, so the
@@ -29,6 +36,9 @@ oracle use): vertices, then edge midpoints with triangle edges
 (1,2), (0,2), (0,1) and tetrahedron edges (2,3), (1,3), (1,2), (0,3), (0,2),
 (0,1). Global P2 dofs are the points of the twice-refined lattice: vertex p
 maps to R(2p) and edge pq to R(p+q), R(I,J,K) = I + (2n+1) J + (2n+1)^2 K.
+On prisms the local dof (a, b) of a triangle dof a and an interval dof b is
+a (p+1) + b, interval dofs ordered bottom, top, then interior (middle);
+the global P2 prism dof of base dof R2 at refined level l is R2 + (2n+1)^2 l.
 """
 from __future__ import annotations
 
@@ -143,12 +153,48 @@ class Mesh:
     def ncells(self) -> int:
         return self.cells.shape[0]
 
+    @property
+    def cell(self) -> int:
+        """Cell code of the library and the oracle: d for simplices, 6 for prisms."""
+        return 6 if self.cells.shape[1] == 6 else self.d
+
 
 def make_mesh(d: int, n: int, jitter_frac: float, rng: np.random.Generator) -> Mesh:
     coords = lattice_coords(n, d)
     coords = jitter(coords, n, jitter_frac, rng)
     cells = square_cells(n) if d == 2 else cube_cells(n)
     return Mesh(d=d, n=n, coords=np.ascontiguousarray(coords), cells=np.ascontiguousarray(cells))
+
+
+def prism_cells(n: int) -> np.ndarray:
+    """Connectivity [2 n^2 n, 6] int32 of the extruded split unit square."""
+    m = n + 1
+    base = square_cells(n).astype(np.int64)              # [T, 3] on the k = 0 layer
+    k = np.arange(n, dtype=np.int64)
+    bot = base[:, None, :] + (m * m) * k[None, :, None]  # [T, n, 3]
+    top = bot + m * m
+    cells = np.stack([bot[..., 0], top[..., 0], bot[..., 1], top[..., 1], bot[..., 2], top[..., 2]], axis=-1)
+    return cells.reshape(-1, 6).astype(np.int32)
+
+
+def make_prism_mesh(n: int, jitter_frac: float, rng: np.random.Generator) -> Mesh:
+    coords = jitter(lattice_coords(n, 3), n, jitter_frac, rng)
+    return Mesh(d=3, n=n, coords=np.ascontiguousarray(coords), cells=np.ascontiguousarray(prism_cells(n)))
+
+
+def prism_p2_dofmap(n: int) -> tuple[np.ndarray, int]:
+    """P2 prism cell->dof map [2 n^2 n, 18] int32 (local order a * 3 + b)."""
+    mr = 2 * n + 1
+    tri, _ = p2_dofmap(square_cells(n), n, 2)            # [T, 6] refined 2-D lattice indices
+    tri = tri.astype(np.int64)
+    k = np.arange(n, dtype=np.int64)
+    levels = np.stack([2 * k, 2 * k + 2, 2 * k + 1], axis=1)   # [n, 3]: bottom, top, middle
+    c2d = tri[:, None, :, None] + (mr * mr) * levels[None, :, None, :]  # [T, n, 6, 3]
+    return c2d.reshape(-1, 18).astype(np.int32), mr ** 3
+
+
+def n_prism_dofs(p: int) -> int:
+    return (p + 1) * (p + 2) // 2 * (p + 1)
 
 
 @dataclass
