@@ -10,7 +10,9 @@
  * fields. These entry points apply that contract to whole meshes on one GPU.
  *
  * Conventions shared by every entry point:
- *  - Reference cells: triangle (0,0),(1,0),(0,1); tetrahedron 0,e1,e2,e3.
+ *  - Reference cells: triangle (0,0),(1,0),(0,1); tetrahedron 0,e1,e2,e3;
+ *    prism T x [0,1] with T the reference triangle (the paper's third cell
+ *    shape, section 5.2).
  *  - Geometry: J has columns x_i - x_0, K = J^{-1} (row-major, so that
  *    d phi/d x_i = sum_a K[a][i] d phi/d X_a, as in Listing 1), integrals use
  *    |det J|. Geometry is always computed in FP64.
@@ -53,7 +55,18 @@ typedef enum {
     COFFEE_E_NOMEM = 6
 } coffee_status;
 
-typedef enum { COFFEE_TRIANGLE = 2, COFFEE_TETRAHEDRON = 3 } coffee_cell; /* value = dimension */
+/* Simplices are numbered by their dimension, the prism by its vertex count.
+ * Prisms (section 5.2 of the paper): cell_to_vertex rows hold six vertices,
+ * each vertex of the base triangle at the bottom, then at the top:
+ * (t0,0), (t0,1), (t1,0), (t1,1), (t2,0), (t2,1). The cell map is spanned by
+ * the six degree-1 prism basis functions, so J, det J and K = J^-1 depend on
+ * the point (a prism need not be an affine image of the reference prism).
+ * The degree-p prism element is the tensor product of the degree-p triangle
+ * (dof order below) and the degree-p interval with nodes 0, 1, then the
+ * interior ones ascending; local dof (a, b) has index a (p + 1) + b. The rule
+ * of degree q is the triangle rule of degree q times Gauss-Legendre with
+ * m = ceil((q+1)/2) points on [0,1], triangle point outermost. */
+typedef enum { COFFEE_TRIANGLE = 2, COFFEE_TETRAHEDRON = 3, COFFEE_PRISM = 6 } coffee_cell;
 
 typedef enum {
     COFFEE_MASS = 0,         /* int f u v                          fields: [f] or none (f = 1)     */
@@ -65,8 +78,12 @@ typedef enum {
                                 fields: [w] (ncomp = d); constants (nu, 1/dt), default (1, 1)   */
     COFFEE_SVK_ENERGY = 4,   /* St Venant-Kirchhoff: int psi(F), F = I + grad u (one value per cell) */
     COFFEE_SVK_RESIDUAL = 5, /* int P(F) : grad v, P = F S (vector of N per cell)                  */
-    COFFEE_SVK_JACOBIAN = 6  /* int dP[du] : grad v (N x N per cell)
+    COFFEE_SVK_JACOBIAN = 6, /* int dP[du] : grad v (N x N per cell)
                                 SVK fields: [u] (ncomp = d); constants (mu, lambda), default (1, 1) */
+    COFFEE_DIFFUSION = 7     /* int kappa dt grad u . grad v: the paper's diffusion kernel, the
+                                Helmholtz operator without its basis-value (mass) term and with
+                                extra constants (section 5.2). No fields; constants (kappa, dt),
+                                default (1, 1)                                                  */
 } coffee_form;
 
 typedef enum {
@@ -107,8 +124,9 @@ typedef struct {
  * the constant weight and basis tables W, X, Y that the kernels of Listings 1
  * and 2 declare, and Table 1). Buffers are caller-owned host memory; pass NULL
  * for all four to query *nq and *ndof. Layouts: points [nq][d], weights [nq],
- * basis [nq][ndof], dbasis [d][nq][ndof] (reference derivatives).
- * quad_degree: q or COFFEE_QUAD(q, rule).
+ * basis [nq][ndof], dbasis [d][nq][ndof] (reference derivatives); d = 3 on
+ * prisms. quad_degree: q or COFFEE_QUAD(q, rule) (on prisms the rule family
+ * applies to the triangle factor).
  * Errors: COFFEE_E_INVALID_ARG (bad cell, degree outside 0..4, a quad_degree
  * naming no rule, null nq/ndof). */
 coffee_status coffee_tabulate(int cell, int degree, int quad_degree, int* nq, int* ndof,
@@ -126,11 +144,17 @@ int coffee_tensor_dim(int form, int cell, int degree);
  * for the energy; FP64 if precision == COFFEE_FP64, else FP32. `out` must be
  * 16-byte aligned. cell_to_vertex and cell_to_dof entries must be valid
  * indices (coffee_check_geometry validates the vertex indices).
+ * Prisms: cell_to_vertex is [ncells][6] (vertex order above) and coords
+ * [nvert][3]; COFFEE_MASS and COFFEE_HELMHOLTZ (no field, or one degree-1
+ * prism field: 6 dofs per cell through cell_to_dof or cell-major) and
+ * COFFEE_DIFFUSION, at degree 1 (6 x 6) and 2 (18 x 18), with the default
+ * rule (q = 2p, 8 and 27 points), in every precision.
  * Errors: COFFEE_E_INVALID_ARG (null pointers, bad enums, negative sizes,
  * misaligned out,
  * field shape/count not matching the form), COFFEE_E_UNSUPPORTED (degree or
  * field degree outside the compiled set, precision not available for the
- * form), COFFEE_E_HIP (launch failure), COFFEE_E_NOMEM (table upload). */
+ * form, a form or rule not compiled for prisms), COFFEE_E_HIP (launch
+ * failure), COFFEE_E_NOMEM (table upload). */
 coffee_status coffee_assemble(int form, int cell, int degree, int quad_degree, int precision,
                               const double* coords, int64_t nvert, const int32_t* cell_to_vertex,
                               int64_t ncells, const coffee_field* coeffs, int ncoeff,
@@ -156,7 +180,9 @@ coffee_status coffee_assemble(int form, int cell, int degree, int quad_degree, i
  *   (a stable sort of the cell-to-vertex / cell-to-dof entries by target):
  *   the result is bitwise reproducible. workspace: device buffer, 256-byte
  *   aligned, of at least coffee_adjoint_workspace_size(...) bytes.
- * COFFEE_SVK_JACOBIAN has no reverse pass (COFFEE_E_UNSUPPORTED).
+ * COFFEE_SVK_JACOBIAN and prism cells have no reverse pass
+ * (COFFEE_E_UNSUPPORTED); COFFEE_DIFFUSION has one at degree 1 and 2 on
+ * triangles and tetrahedra (constants kappa, dt).
  * Errors as coffee_assemble, plus COFFEE_E_BUFFER_TOO_SMALL (workspace),
  * COFFEE_E_INVALID_ARG (deterministic not 0/1; NULL workspace with
  * deterministic = 1; NULL lam or u where the form needs them). */
@@ -308,7 +334,9 @@ coffee_status coffee_assemble_csr(int form, int cell, int degree, int quad_degre
  * Fig. 1: the Jacobian of the affine map and its determinant, which the
  * kernels invert and use as |det J| without checking): writes to *first_bad
  * (device int64) the smallest cell index with a vertex index outside
- * [0, nvert), a non-finite coordinate or det J <= 0, or -1 if none.
+ * [0, nvert), a non-finite coordinate or det J <= 0, or -1 if none. On
+ * prisms (non-affine) det J is tested at the six reference vertices and at
+ * the mid-heights of the three vertical edges.
  * Errors: COFFEE_E_INVALID_ARG. */
 coffee_status coffee_check_geometry(int cell, const double* coords, int64_t nvert,
                                     const int32_t* cell_to_vertex, int64_t ncells,

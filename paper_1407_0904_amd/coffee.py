@@ -17,8 +17,10 @@ import torch
 _SO = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcoffee.so")
 
 FORMS = {"mass": 0, "helmholtz": 1, "elasticity": 2, "burgers": 3,
-         "svk_energy": 4, "svk_residual": 5, "svk_jacobian": 6}
-CELLS = {"triangle": 2, "tetrahedron": 3, 2: 2, 3: 3}
+         "svk_energy": 4, "svk_residual": 5, "svk_jacobian": 6, "diffusion": 7}
+# cell codes: simplices by dimension, the prism (triangle x interval) by its vertex count
+CELLS = {"triangle": 2, "tetrahedron": 3, "prism": 6, 2: 2, 3: 3, 6: 6}
+PRISM = 6
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
@@ -125,8 +127,19 @@ def _stream(stream):
 
 # Shape checks. They run before any device pointer is taken, so a wrong shape
 # is a ValueError on the host instead of an out-of-bounds access on the GPU.
-def _nloc(d: int, p: int) -> int:
-    return (p + 1) * (p + 2) // 2 if d == 2 else (p + 1) * (p + 2) * (p + 3) // 6
+def _nloc(c: int, p: int) -> int:
+    """Lagrange dofs of degree p on cell code c."""
+    if c == PRISM:
+        return (p + 1) * (p + 2) // 2 * (p + 1)
+    return (p + 1) * (p + 2) // 2 if c == 2 else (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def _sdim(c: int) -> int:
+    return 3 if c == PRISM else c
+
+
+def _nverts(c: int) -> int:
+    return 6 if c == PRISM else c + 1
 
 
 def _need(t, name, dtype, shape=None, numel=None, allow_none=False):
@@ -149,13 +162,14 @@ def _nm(name):
     return name() if callable(name) else name
 
 
-def _check_mesh(d, coords, cell_to_vertex, where=""):
+def _check_mesh(c, coords, cell_to_vertex, where=""):
     _need(coords, lambda: where + "coords", torch.float64)
     _need(cell_to_vertex, lambda: where + "cell_to_vertex", torch.int32)
+    d, nv = _sdim(c), _nverts(c)
     if coords.ndim != 2 or coords.shape[1] != d:
         raise ValueError(f"{where}coords has shape {tuple(coords.shape)}, expected (nvert, {d})")
-    if cell_to_vertex.ndim != 2 or cell_to_vertex.shape[1] != d + 1:
-        raise ValueError(f"{where}cell_to_vertex has shape {tuple(cell_to_vertex.shape)}, expected (ncells, {d + 1})")
+    if cell_to_vertex.ndim != 2 or cell_to_vertex.shape[1] != nv:
+        raise ValueError(f"{where}cell_to_vertex has shape {tuple(cell_to_vertex.shape)}, expected (ncells, {nv})")
 
 
 def _check_fields(coeffs, d, ncells, where="coeffs"):
@@ -200,13 +214,13 @@ def _fields(coeffs):
 
 
 def coffee_tabulate(cell, degree: int, quad_degree: int):
-    """Host FP64 tables: (points [nq, d], weights [nq], basis [nq, n], dbasis [d, nq, n])."""
+    """Host FP64 tables: (points [nq, d], weights [nq], basis [nq, n], dbasis [d, nq, n]); d = 3 on prisms."""
     c = CELLS[cell]
     nq, nd = C.c_int(), C.c_int()
     _check(_lib.coffee_tabulate(c, degree, quad_degree, C.byref(nq), C.byref(nd), None, None, None, None),
            "coffee_tabulate")
-    q, n = nq.value, nd.value
-    X = np.zeros((q, c)); W = np.zeros(q); B = np.zeros((q, n)); D = np.zeros((c, q, n))
+    q, n, d = nq.value, nd.value, _sdim(c)
+    X = np.zeros((q, d)); W = np.zeros(q); B = np.zeros((q, n)); D = np.zeros((d, q, n))
     _check(_lib.coffee_tabulate(c, degree, quad_degree, C.byref(nq), C.byref(nd), X.ctypes.data,
                                 W.ctypes.data, B.ctypes.data, D.ctypes.data), "coffee_tabulate")
     return X, W, B, D

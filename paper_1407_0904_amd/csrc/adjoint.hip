@@ -493,6 +493,10 @@ static const std::vector<AdjEntry>& adj_registry() {
         {F_BURG, 2, 1, 1, &launch_adjoint<F_BURG, 2, 1, 1>},
         {F_BURG, 3, 1, 1, &launch_adjoint<F_BURG, 3, 1, 1>},
         {F_BURG, 3, 2, 2, &launch_adjoint<F_BURG, 3, 2, 2>},
+        {F_DIFF, 2, 1, 0, &launch_adjoint<F_DIFF, 2, 1, 0>},
+        {F_DIFF, 2, 2, 0, &launch_adjoint<F_DIFF, 2, 2, 0>},
+        {F_DIFF, 3, 1, 0, &launch_adjoint<F_DIFF, 3, 1, 0>},
+        {F_DIFF, 3, 2, 0, &launch_adjoint<F_DIFF, 3, 2, 0>},
     };
     return reg;
 }
@@ -570,6 +574,8 @@ coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, cons
     } else if (form == COFFEE_ELASTICITY && ncoeff == 0) {
         a.L.c0 = constants[0];
         a.L.c1 = constants[1];
+    } else if (form == COFFEE_DIFFUSION) {
+        a.L.c0 = (nconst > 0 ? constants[0] : 1.0) * (nconst > 1 ? constants[1] : 1.0);  // kappa dt
     }
     a.R = R;
     a.lam = lam;

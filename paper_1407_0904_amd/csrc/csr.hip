@@ -255,7 +255,7 @@ extern "C" coffee_status coffee_assemble_csr(int form, int cell, int degree, int
     if (form == COFFEE_SVK_ENERGY || form == COFFEE_SVK_RESIDUAL) return COFFEE_E_UNSUPPORTED;
     const int N = coffee_tensor_dim(form, cell, degree);
     if (N <= 0) return COFFEE_E_INVALID_ARG;
-    const int n = n_scalar(cell, degree), nc = N / n;
+    const int n = cell_nscalar(cell, degree), nc = N / n;
     if (degree > 1 && !cell_to_dof) return COFFEE_E_INVALID_ARG;  // P1: the vertices are the dofs
     const int32_t* map = cell_to_dof ? cell_to_dof : c2v;
     if (ndofs < 1 || nnz < 0 || (nnz > 0 && (!row_ptr || !col_idx || !values))) return COFFEE_E_INVALID_ARG;
@@ -277,12 +277,12 @@ extern "C" coffee_status coffee_assemble_csr(int form, int cell, int degree, int
         for (int i = 0; i < ncoeff; ++i) {
             // the chunk's cells: offset the dof map, or the cell-major values
             fl[i] = coeffs[i];
-            const int64_t nl = n_scalar(cell, coeffs[i].degree);
+            const int64_t nl = cell_nscalar(cell, coeffs[i].degree);
             if (coeffs[i].cell_to_dof) fl[i].cell_to_dof = coeffs[i].cell_to_dof + e0 * nl;
             else if (coeffs[i].values) fl[i].values = coeffs[i].values + e0 * nl * coeffs[i].ncomp;
         }
         coffee_status st = coffee_assemble(form, cell, degree, quad_degree, precision, coords, nvert,
-                                           c2v + e0 * (cell + 1), m, fl, ncoeff, constants, nconst, workspace,
+                                           c2v + e0 * cell_nverts(cell), m, fl, ncoeff, constants, nconst, workspace,
                                            hip_stream);
         if (st != COFFEE_OK) return st;
         const int64_t work = m * N;

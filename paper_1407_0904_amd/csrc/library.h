@@ -28,7 +28,8 @@ coffee_status adjoint_linear(int form, int cell, int degree, int q, int fd, cons
 void free_adjoint_tables();
 coffee_status reference_table_f64(int dev, int form, int dim, int p, int q, int fd, const double** out);
 coffee_status assemble_p1(int form, int cell, int fd, int q, int precision, const double* coords, const int32_t* c2v,
-                          int64_t ncells, const coffee_field* coeffs, int ncoeff, void* out, void* hip_stream);
+                          int64_t ncells, const coffee_field* coeffs, int ncoeff, const double* constants, int nconst,
+                          void* out, void* hip_stream);
 coffee_status get_rtable_public(int dev, int form, int dim, int p, int q, int fd, int prec, const void** out);
 // Host bytes of the packed reference fragments and of the FP64 reference tensors.
 bool rtable_bytes(int form, int dim, int p, int q, int fd, int prec, std::vector<char>& buf);
@@ -43,6 +44,23 @@ coffee_status assemble_svk_bf16(int form, int cell, int degree, int q, const dou
                                 void* out, void* hip_stream);
 void free_svkb_tables();
 int num_cu(int dev);
+
+struct RefTensor;
+// Reference tensors packed in MFMA B-fragment order (library.hip).
+std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym, int rows_per_group);
+
+// Prism cells (prism.hip).
+coffee_status assemble_prism(int form, int degree, int quad, int precision, const double* coords,
+                             const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, int ncoeff,
+                             const double* constants, int nconst, void* out, void* hip_stream);
+void free_prism_tables();
+
+inline bool is_svk_form(int form) {
+    return form == COFFEE_SVK_ENERGY || form == COFFEE_SVK_RESIDUAL || form == COFFEE_SVK_JACOBIAN;
+}
+// Vertices per cell and scalar Lagrange dofs of degree p for a cell code.
+inline int cell_nverts(int cell) { return cell == COFFEE_PRISM ? 6 : cell + 1; }
+int cell_nscalar(int cell, int p);
 
 // Deterministic scatter of per-cell gradients (scatter.hip). One target array:
 // `n` local entries of `ncomp` values (entry j = cell * slots + slot), added to

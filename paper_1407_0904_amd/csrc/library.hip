@@ -30,6 +30,7 @@ static std::vector<LinEntry>& lin_registry() {
         register_helmholtz_tet(reg);
         register_elasticity(reg);
         register_burgers(reg);
+        register_diffusion(reg);
         register_variants(reg);
     });
     return reg;
@@ -95,7 +96,7 @@ static float bf16_float_host(uint16_t h) {
 // the entries a <= b of the upper triangle in row-major order (symmetric
 // engine), or the entries ab = a n + b in row groups of `rows_per_group` rows,
 // each group starting on a fresh 16-column tile (vector engine).
-static std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym, int rows_per_group) {
+std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym, int rows_per_group) {
     const int NS = R.NS, NN = R.NS * R.NS, KR = R.KR;
     std::vector<int> colmap;  // packed column -> entry, -1 for padding
     if (sym) {
@@ -246,11 +247,16 @@ extern "C" const char* coffee_status_string(int s) {
     }
 }
 
+int coffee::cell_nscalar(int cell, int p) { return cell == COFFEE_PRISM ? n_prism(p) : n_scalar(cell, p); }
+
 extern "C" int coffee_tensor_dim(int form, int cell, int degree) {
-    if ((cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) || degree < 1 || degree > kMaxP) return -1;
+    if (degree < 1 || degree > kMaxP) return -1;
+    if (cell == COFFEE_PRISM)
+        return (form == COFFEE_MASS || form == COFFEE_HELMHOLTZ || form == COFFEE_DIFFUSION) ? n_prism(degree) : -1;
+    if (cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) return -1;
     const int n = n_scalar(cell, degree);
     switch (form) {
-        case COFFEE_MASS: case COFFEE_HELMHOLTZ: return n;
+        case COFFEE_MASS: case COFFEE_HELMHOLTZ: case COFFEE_DIFFUSION: return n;
         case COFFEE_ELASTICITY: case COFFEE_BURGERS: case COFFEE_SVK_RESIDUAL: case COFFEE_SVK_JACOBIAN:
             return cell * n;
         case COFFEE_SVK_ENERGY: return 0;
@@ -263,16 +269,21 @@ coffee_status coffee::validate_common(int form, int cell, int degree, int quad_d
                                       int64_t nvert, const int32_t* c2v, int64_t ncells,
                                       const coffee_field* coeffs, int ncoeff, const double* constants,
                                       int nconst, int* q_out, int* fd_out) {
-    if (form < COFFEE_MASS || form > COFFEE_SVK_JACOBIAN) return COFFEE_E_INVALID_ARG;
-    if (cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) return COFFEE_E_INVALID_ARG;
+    if (form < COFFEE_MASS || form > COFFEE_DIFFUSION) return COFFEE_E_INVALID_ARG;
+    if (cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON && cell != COFFEE_PRISM) return COFFEE_E_INVALID_ARG;
     if (degree < 1 || degree > kMaxP) return COFFEE_E_INVALID_ARG;
+    const bool prism = cell == COFFEE_PRISM;
     // quad_degree: q or COFFEE_QUAD(q, rule); negative selects the default
-    if (quad_degree >= 0 && rule_size(cell == COFFEE_TRIANGLE ? 2 : 3, quad_degree) <= 0) return COFFEE_E_INVALID_ARG;
+    if (quad_degree >= 0 &&
+        (prism ? prism_rule_size(quad_degree) : rule_size(cell == COFFEE_TRIANGLE ? 2 : 3, quad_degree)) <= 0)
+        return COFFEE_E_INVALID_ARG;
+    if (prism && form != COFFEE_MASS && form != COFFEE_HELMHOLTZ && form != COFFEE_DIFFUSION)
+        return COFFEE_E_UNSUPPORTED;
     if (ncells < 0 || nvert < 0 || nvert > INT32_MAX) return COFFEE_E_INVALID_ARG;
     if (ncells > 0 && (!coords || !c2v)) return COFFEE_E_INVALID_ARG;
     if (ncoeff < 0 || ncoeff > 2 || (ncoeff > 0 && !coeffs)) return COFFEE_E_INVALID_ARG;
     if (nconst < 0 || (nconst > 0 && !constants)) return COFFEE_E_INVALID_ARG;
-    const int d = cell;
+    const int d = prism ? 3 : cell;
     for (int i = 0; i < ncoeff; ++i) {
         if (!coeffs[i].values && ncells > 0) return COFFEE_E_INVALID_ARG;
         if (coeffs[i].degree < 1 || coeffs[i].degree > kMaxP) return COFFEE_E_INVALID_ARG;
@@ -285,7 +296,11 @@ coffee_status coffee::validate_common(int form, int cell, int degree, int quad_d
             if (ncoeff == 1) {
                 if (coeffs[0].ncomp != 1) return COFFEE_E_INVALID_ARG;
                 fd = coeffs[0].degree;
+                if (prism && fd != 1) return COFFEE_E_UNSUPPORTED;
             }
+            break;
+        case COFFEE_DIFFUSION:
+            if (ncoeff != 0) return COFFEE_E_INVALID_ARG;
             break;
         case COFFEE_ELASTICITY:
             if (ncoeff == 0) {
@@ -301,7 +316,7 @@ coffee_status coffee::validate_common(int form, int cell, int degree, int quad_d
             fd = coeffs[0].degree;
     }
     int q = quad_degree >= 0 ? quad_degree : (form == COFFEE_BURGERS ? 2 * degree + 1 : 2 * degree);
-    if (rule_size(d, q) <= 0) return COFFEE_E_UNSUPPORTED;
+    if ((prism ? prism_rule_size(q) : rule_size(d, q)) <= 0) return COFFEE_E_UNSUPPORTED;
     *q_out = q;
     *fd_out = fd;
     return COFFEE_OK;
@@ -318,12 +333,17 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     if (precision < COFFEE_FP64 || precision > COFFEE_BF16X3) return COFFEE_E_INVALID_ARG;
     if (ncells > 0 && !out) return COFFEE_E_INVALID_ARG;
     if (((uintptr_t)out & 15) != 0) return COFFEE_E_INVALID_ARG;
-    if (form >= COFFEE_SVK_ENERGY)
+    if (cell == COFFEE_PRISM)
+        return assemble_prism(form, degree, q, precision, coords, c2v, ncells, coeffs, ncoeff, constants, nconst, out,
+                              hip_stream);
+    if (is_svk_form(form))
         return assemble_svk(form, cell, degree, q, precision, coords, nvert, c2v, ncells, coeffs, constants,
                             nconst, out, hip_stream);
-    // degree 1 mass / Helmholtz: thread-per-cell FMA kernel (p1.hip)
-    if ((form == COFFEE_MASS || form == COFFEE_HELMHOLTZ) && degree == 1 && fd <= 1 && precision != COFFEE_BF16X3)
-        return assemble_p1(form, cell, fd, q, precision, coords, c2v, ncells, coeffs, ncoeff, out, hip_stream);
+    // degree 1 mass / Helmholtz / diffusion: thread-per-cell FMA kernel (p1.hip)
+    if ((form == COFFEE_MASS || form == COFFEE_HELMHOLTZ || form == COFFEE_DIFFUSION) && degree == 1 && fd <= 1 &&
+        precision != COFFEE_BF16X3)
+        return assemble_p1(form, cell, fd, q, precision, coords, c2v, ncells, coeffs, ncoeff, constants, nconst, out,
+                           hip_stream);
     int tuned_variant = 0;
     const int tuned = tuned_linear(form, cell, degree, fd, precision, &tuned_variant);
     const LinEntry* e = find_linear(form, cell, degree, fd, precision, t_variant >= 0 ? t_variant : tuned_variant);
@@ -347,6 +367,8 @@ extern "C" coffee_status coffee_assemble(int form, int cell, int degree, int qua
     } else if (form == COFFEE_ELASTICITY && ncoeff == 0) {
         a.c0 = constants[0];
         a.c1 = constants[1];
+    } else if (form == COFFEE_DIFFUSION) {
+        a.c0 = (nconst > 0 ? constants[0] : 1.0) * (nconst > 1 ? constants[1] : 1.0);  // kappa dt
     }
     a.rfrag = rf;
     a.out = out;
@@ -389,6 +411,42 @@ __global__ void k_check_geometry(const double* coords, const int32_t* c2v, int64
     }
 }
 
+// Prisms: the map is not affine, so det J is checked at nine points: the six
+// reference vertices and the mid-heights of the three vertical edges (det J
+// is linear in (X, Y) on each horizontal slice and quadratic in Z).
+__global__ void k_check_geometry_prism(const double* coords, const int32_t* c2v, int64_t ncells, int64_t nvert,
+                                       unsigned long long* first_bad) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncells;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double x[6][3];
+        bool bad = false;
+        for (int v = 0; v < 6; ++v) {
+            const int64_t g = c2v[e * 6 + v];
+            if (g < 0 || g >= nvert) { bad = true; break; }
+            for (int i = 0; i < 3; ++i) {
+                x[v][i] = coords[g * 3 + i];
+                if (!isfinite(x[v][i])) bad = true;
+            }
+        }
+        for (int pt = 0; pt < 9 && !bad; ++pt) {
+            const int t = pt % 3;
+            const double X = t == 1 ? 1.0 : 0.0, Y = t == 2 ? 1.0 : 0.0, Z = 0.5 * (pt / 3);
+            const double zb = 1.0 - Z, l0 = 1.0 - X - Y;
+            double J[3][3];
+            for (int i = 0; i < 3; ++i) {
+                J[i][0] = zb * (x[2][i] - x[0][i]) + Z * (x[3][i] - x[1][i]);
+                J[i][1] = zb * (x[4][i] - x[0][i]) + Z * (x[5][i] - x[1][i]);
+                J[i][2] = l0 * (x[1][i] - x[0][i]) + X * (x[3][i] - x[2][i]) + Y * (x[5][i] - x[4][i]);
+            }
+            const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                               J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            bad = !(det > 0.0) || !isfinite(det);
+        }
+        if (bad) atomicMin(first_bad, (unsigned long long)e);
+    }
+}
+
 template <typename T>
 __global__ void k_fill(T* p, T v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -398,7 +456,7 @@ __global__ void k_fill(T* p, T v, int64_t n) {
 extern "C" coffee_status coffee_check_geometry(int cell, const double* coords, int64_t nvert,
                                                const int32_t* c2v, int64_t ncells, int64_t* first_bad,
                                                void* hip_stream) {
-    if (cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) return COFFEE_E_INVALID_ARG;
+    if (cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON && cell != COFFEE_PRISM) return COFFEE_E_INVALID_ARG;
     if (!first_bad || ncells < 0 || nvert < 0 || (ncells > 0 && (!coords || !c2v))) return COFFEE_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)hip_stream;
     // the sentinel ~0 read as int64 is -1 ("no bad cell")
@@ -406,7 +464,9 @@ extern "C" coffee_status coffee_check_geometry(int cell, const double* coords, i
     hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, s, fb, ~0ull, (int64_t)1);
     if (ncells > 0) {
         const int grid = (int)std::min<int64_t>((ncells + 255) / 256, 4096);
-        if (cell == 2)
+        if (cell == COFFEE_PRISM)
+            hipLaunchKernelGGL(k_check_geometry_prism, dim3(grid), dim3(256), 0, s, coords, c2v, ncells, nvert, fb);
+        else if (cell == 2)
             hipLaunchKernelGGL((k_check_geometry<2>), dim3(grid), dim3(256), 0, s, coords, c2v, ncells, nvert, fb);
         else
             hipLaunchKernelGGL((k_check_geometry<3>), dim3(grid), dim3(256), 0, s, coords, c2v, ncells, nvert, fb);
@@ -418,6 +478,7 @@ extern "C" void coffee_shutdown(void) {
     free_adjoint_tables();
     free_svk_tables();
     free_svkb_tables();
+    free_prism_tables();
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);

@@ -85,7 +85,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
-enum { F_MASS = 0, F_HELM = 1, F_ELAST = 2, F_BURG = 3 };
+// same values as the public coffee_form enum
+enum { F_MASS = 0, F_HELM = 1, F_ELAST = 2, F_BURG = 3, F_DIFF = 7 };
 
 constexpr int nsc(int d, int p) { return d == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6; }
 constexpr int npair(int d) { return d * (d + 1) / 2; }
@@ -94,6 +95,7 @@ constexpr int ncomp_space(int form, int d) { return (form == F_ELAST || form == 
 constexpr int kref(int form, int d, int fd) {
     return form == F_MASS   ? nfield(d, fd)
          : form == F_HELM   ? npair(d) + nfield(d, fd)
+         : form == F_DIFF   ? npair(d)
          : form == F_ELAST  ? nfield(d, fd) * d * d
                             : 1 + npair(d) + 2 * nfield(d, fd) * d;
 }
@@ -112,7 +114,7 @@ struct LinArgs {
     const int32_t* c2v;
     int64_t ncells;
     FieldArg f0, f1;
-    double c0, c1;          // elasticity (mu, lambda) if no fields; Burgers (nu, 1/dt)
+    double c0, c1;          // elasticity (mu, lambda) if no fields; Burgers (nu, 1/dt); diffusion c0 = kappa dt
     const void* rfrag;      // packed reference fragments
     void* out;
     int64_t nchunks;        // ceil(ncells / 256)
@@ -272,8 +274,9 @@ __host__ __device__ inline void build_G(const CellData<FORM, D, FD, T>& cd, cons
     const auto& K = cd.g.K;
     const T ad = cd.g.adet;
     int t = 0;
-    if constexpr (FORM == F_HELM || FORM == F_BURG) {
-        const T sc = (FORM == F_BURG) ? ad * A.c0 : ad;  // nu for Burgers
+    if constexpr (FORM == F_HELM || FORM == F_BURG || FORM == F_DIFF) {
+        // nu for Burgers, kappa dt for diffusion
+        const T sc = (FORM == F_BURG || FORM == F_DIFF) ? T(ad * A.c0) : ad;
         if constexpr (FORM == F_BURG) G[t++] = (C1 == C2) ? ad * A.c1 : T(0.0);
 #pragma unroll
         for (int a = 0; a < D; ++a)
@@ -335,8 +338,8 @@ __host__ __device__ inline void reverse_G(const CellData<FORM, D, FD>& cd, const
     const auto& K = cd.g.K;
     const double ad = cd.g.adet;
     int t = 0;
-    if constexpr (FORM == F_HELM || FORM == F_BURG) {
-        const double sc = (FORM == F_BURG) ? ad * A.c0 : ad;
+    if constexpr (FORM == F_HELM || FORM == F_BURG || FORM == F_DIFF) {
+        const double sc = (FORM == F_BURG || FORM == F_DIFF) ? ad * A.c0 : ad;
         if constexpr (FORM == F_BURG) {
             // (1/dt) |det J|: no K or coefficient dependence
             if (C1 == C2) S += ad * A.c1 * gbar(t);

@@ -1,4 +1,4 @@
-// Degree-1 mass and Helmholtz: one thread per cell, FMA arithmetic (the
+// Degree-1 mass, Helmholtz and diffusion: one thread per cell, FMA arithmetic (the
 // per-cell arithmetic is in p1.hpp). Each lane gathers its cell, forms J,
 // |det J|, K = J^-1 and the G row in FP64 registers and writes its tensor to
 // an LDS row; the wave's 64 tensors then leave as stores whose 64 lanes cover
@@ -54,10 +54,11 @@ static hipError_t launch_p1(const dev::LinArgs& a, const double* R, int prec, hi
     return hipGetLastError();
 }
 
-// Mass or Helmholtz at degree 1 with no field or a P1 field, FP64 or FP32
+// Mass, Helmholtz or diffusion at degree 1 with no field or a P1 field, FP64 or FP32
 // (BF16X3 and every other case take the MFMA engines).
 coffee_status assemble_p1(int form, int cell, int fd, int q, int precision, const double* coords, const int32_t* c2v,
-                          int64_t ncells, const coffee_field* coeffs, int ncoeff, void* out, void* hip_stream) {
+                          int64_t ncells, const coffee_field* coeffs, int ncoeff, const double* constants, int nconst,
+                          void* out, void* hip_stream) {
     if (ncells == 0) return COFFEE_OK;
     if (ncells > (int64_t)INT32_MAX * 64) return COFFEE_E_UNSUPPORTED;
     int dev = 0;
@@ -75,7 +76,10 @@ coffee_status assemble_p1(int form, int cell, int fd, int q, int precision, cons
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e;
     const bool helm = form == COFFEE_HELMHOLTZ;
-    if (cell == 2) {
+    if (form == COFFEE_DIFFUSION) {
+        a.c0 = (nconst > 0 ? constants[0] : 1.0) * (nconst > 1 ? constants[1] : 1.0);  // kappa dt
+        e = cell == 2 ? launch_p1<dev::F_DIFF, 2, 0>(a, R, precision, s) : launch_p1<dev::F_DIFF, 3, 0>(a, R, precision, s);
+    } else if (cell == 2) {
         if (fd == 0) e = helm ? launch_p1<dev::F_HELM, 2, 0>(a, R, precision, s) : launch_p1<dev::F_MASS, 2, 0>(a, R, precision, s);
         else e = helm ? launch_p1<dev::F_HELM, 2, 1>(a, R, precision, s) : launch_p1<dev::F_MASS, 2, 1>(a, R, precision, s);
     } else {

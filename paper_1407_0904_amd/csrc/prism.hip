@@ -1,0 +1,442 @@
+// Prism cells (triangle x interval): mass, Helmholtz and diffusion.
+//
+// The paper's benchmarks run on prisms as well as on simplices (section 5.2;
+// at p = 1 a prism's j and k loops have 6 iterations). A prism is the image
+// of the reference prism under the map spanned by its six degree-1 basis
+// functions; that map is not affine, so J, det J and K = J^-1 change from
+// quadrature point to point and the quadrature sum cannot be folded into
+// point-free reference tensors as on simplices (the point loop carries the
+// geometry). It stays the contraction of section 3.3's outer-product form,
+// with the point index inside K:
+//     A[e][a][b] = sum_{q, j} G[e][q, j] R[q, j][a][b]
+//     G[e][q, j] = W_q |det J_q| (K_q K_q^T)_{al be}   (j over al <= be; kappa dt for diffusion)
+//                  W_q |det J_q| f(X_q)                 (mass term; f = 1 without a field)
+//     R[q, j][a][b] = d_al phi_a d_be phi_b (+ d_be phi_a d_al phi_b for al != be), phi_a phi_b at X_q
+// so K = nq x (6 + 1) for Helmholtz, nq x 6 for diffusion, nq for mass. Over
+// 16 cells this is a 16 x K by K x 16 product per 16 unique entries (a <= b;
+// the matrices are symmetric), on the same MFMA instructions as the simplex
+// engines (linear.hpp).
+//
+// Per wave: one tile of 16 cells at a time. The 64 lanes are 16 cells x 4
+// groups of quadrature points: each lane gathers its cell (all four lanes of
+// a cell read the same lines), forms J, K and |det J| in FP64 at its points
+// and writes those G entries to the tile's LDS rows. The MFMA loop then runs
+// over all n-tiles at once, and the 16 element matrices leave through LDS as
+// contiguous 16-byte stores (the staging area reuses the G rows).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "library.h"
+#include "linear.hpp"
+#include "tables.h"
+
+namespace coffee {
+namespace dev {
+
+typedef unsigned int u32x4p __attribute__((ext_vector_type(4)));
+
+constexpr int prism_ns(int p) { return (p + 1) * (p + 2) / 2 * (p + 1); }
+// G entries per point: the six pairs al <= be, then the mass term
+constexpr int prism_jq(int form) { return form == F_MASS ? 1 : (form == F_HELM ? 7 : 6); }
+
+template <int FORM, int P, int FD, int PREC, int NQ>
+struct PrismCfg {
+    using g_t = typename PrecT<PREC>::gtype;
+    using frag_t = typename PrecT<PREC>::frag;
+    using acc_t = typename PrecT<PREC>::acc;
+    using out_t = typename PrecT<PREC>::otype;
+    static constexpr int NS = prism_ns(P);
+    static constexpr int NN = NS * NS;
+    static constexpr int NU = NS * (NS + 1) / 2;
+    static constexpr int NT = (NU + 15) / 16;
+    static constexpr int JQ = prism_jq(FORM);
+    static constexpr int KR = NQ * JQ;
+    static constexpr int KE = PREC == PREC_BF16X3 ? 3 * KR : KR;
+    static constexpr int KS = (KE + kstep(PREC) - 1) / kstep(PREC);
+    // odd FP64/FP32 rows spread a fragment's 16 rows over the banks; BF16
+    // rows stay 16-byte aligned
+    static constexpr int ROW = PREC == PREC_BF16X3 ? KS * 32 + 8 : KS * 4 + 1;
+    static constexpr int GT_BYTES = 16 * ROW * (int)sizeof(g_t);
+    static constexpr int ST_BYTES = 8 * NN * (int)sizeof(out_t);
+    static constexpr int WAVE_BYTES = ((GT_BYTES > ST_BYTES ? GT_BYTES : ST_BYTES) + 15) / 16 * 16;
+    // two waves per workgroup when four would take more than half the LDS
+    static constexpr int WAVES = 4 * WAVE_BYTES <= 80 * 1024 ? 4 : 2;
+    static constexpr int LDS_BYTES = WAVES * WAVE_BYTES;
+    static constexpr int REGB = NT * KS * (PREC == PREC_F64 ? 2 : (PREC == PREC_F32 ? 1 : 4));
+    static constexpr bool RREG = REGB <= 64;  // reference fragments held in registers
+};
+
+struct PrismArgs {
+    const double* coords;  // [nvert][3]
+    const int32_t* c2v;    // [ncells][6]
+    int64_t ncells;
+    FieldArg f;            // degree-1 prism field (6 dofs per cell); values NULL: none
+    double kdt;            // kappa dt (diffusion)
+    const double* qtab;    // [NQ][4]: X, Y, Z, W
+    const void* rfrag;     // packed reference fragments
+    void* out;
+    int64_t ntiles;        // ceil(ncells / 16)
+};
+
+// K = J^-1 (K[a][i] = d X_a / d x_i, J[i][a] = d x_i / d X_a) and |det J|.
+__device__ inline void prism_inverse(const double (&J)[3][3], double (&K)[3][3], double& adet) {
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double r = 1.0 / det;
+    K[0][0] = c00 * r;
+    K[1][0] = c01 * r;
+    K[2][0] = c02 * r;
+    K[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+    K[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+    K[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+    K[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+    K[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+    K[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+    adet = fabs(det);
+}
+
+// One G value into LDS column k (with the hi/lo split for BF16X3: columns k,
+// KR + k hold the high part, 2 KR + k the low part, against R's (hi, lo, hi)).
+template <int PREC, int KR>
+__device__ inline void put_g(typename PrecT<PREC>::gtype* row, int k, double g) {
+    if constexpr (PREC == PREC_F64) {
+        row[k] = g;
+    } else if constexpr (PREC == PREC_F32) {
+        row[k] = (float)g;
+    } else {
+        const float x = (float)g;
+        const u16 hi = bf16_bits_rne(x);
+        row[k] = hi;
+        row[KR + k] = hi;
+        row[2 * KR + k] = bf16_bits_rne(x - bf16_to_float(hi));
+    }
+}
+
+template <int FORM, int P, int FD, int PREC, int NQ>
+__global__ __launch_bounds__(256) void k_prism(PrismArgs A) {
+    using C = PrismCfg<FORM, P, FD, PREC, NQ>;
+    using g_t = typename C::g_t;
+    using frag_t = typename C::frag_t;
+    using acc_t = typename C::acc_t;
+    using out_t = typename C::out_t;
+    constexpr int NS = C::NS, NN = C::NN, NU = C::NU, NT = C::NT, KS = C::KS, ROW = C::ROW, JQ = C::JQ,
+                  KR = C::KR;
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, grp = lane >> 4;
+    g_t* gt = reinterpret_cast<g_t*>(lds + wave * C::WAVE_BYTES);
+    out_t* st = reinterpret_cast<out_t*>(lds + wave * C::WAVE_BYTES);
+    const frag_t* rf = reinterpret_cast<const frag_t*>(A.rfrag);
+    out_t* out = reinterpret_cast<out_t*>(A.out);
+
+    // (a, b) of the unique entry u = 16 t + col, a <= b, row-major over the upper triangle
+    int ua[NT], ub[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        int u = t * 16 + col, a = 0;
+        while (a < NS - 1 && u >= NS - a) { u -= NS - a; ++a; }
+        ua[t] = a;
+        ub[t] = a + u;
+    }
+    frag_t rreg[C::RREG ? NT : 1][C::RREG ? KS : 1];
+    if constexpr (C::RREG) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) rreg[t][s] = gload(rf + (t * KS + s) * 64 + lane);
+    }
+
+    const int64_t stride = (int64_t)gridDim.x * C::WAVES;
+    for (int64_t tile = (int64_t)blockIdx.x * C::WAVES + wave; tile < A.ntiles; tile += stride) {
+        const int64_t base = tile * 16;
+        const int64_t cell = base + col;
+        const bool valid = cell < A.ncells;
+        const int64_t cc = valid ? cell : A.ncells - 1;
+
+        // gather: six vertices (each base vertex at the bottom, then the top)
+        double x[6][3], f[6];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            const int64_t g = gload(A.c2v + cc * 6 + v);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) x[v][i] = gload(A.coords + g * 3 + i);
+        }
+        if constexpr (FD > 0) {
+#pragma unroll
+            for (int v = 0; v < 6; ++v) {
+                const int64_t src = A.f.map ? (int64_t)gload(A.f.map + cc * 6 + v) : cc * 6 + v;
+                f[v] = gload(A.f.values + src);
+            }
+        }
+
+        // G entries of this lane's points q = grp, grp + 4, ...
+        g_t* row = gt + col * ROW;
+#pragma unroll 1
+        for (int q = grp; q < NQ; q += 4) {
+            const double X = gload(A.qtab + 4 * q), Y = gload(A.qtab + 4 * q + 1);
+            const double Z = gload(A.qtab + 4 * q + 2), W = gload(A.qtab + 4 * q + 3);
+            const double zb = 1.0 - Z, l0 = 1.0 - X - Y;
+            double J[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                J[i][0] = zb * (x[2][i] - x[0][i]) + Z * (x[3][i] - x[1][i]);
+                J[i][1] = zb * (x[4][i] - x[0][i]) + Z * (x[5][i] - x[1][i]);
+                J[i][2] = l0 * (x[1][i] - x[0][i]) + X * (x[3][i] - x[2][i]) + Y * (x[5][i] - x[4][i]);
+            }
+            double K[3][3], adet;
+            prism_inverse(J, K, adet);
+            const double w = valid ? W * adet : 0.0;
+            int j = q * JQ;
+            if constexpr (FORM != F_MASS) {
+                const double sc = FORM == F_DIFF ? w * A.kdt : w;
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int be = al; be < 3; ++be) {
+                        const double s = K[al][0] * K[be][0] + K[al][1] * K[be][1] + K[al][2] * K[be][2];
+                        put_g<PREC, KR>(row, j++, sc * s);
+                    }
+            }
+            if constexpr (FORM != F_DIFF) {
+                double fq = 1.0;
+                if constexpr (FD > 0) {
+                    // degree-1 prism basis lambda_t(X, Y) l_s(Z) at the point
+                    fq = (l0 * f[0] + X * f[2] + Y * f[4]) * zb + (l0 * f[1] + X * f[3] + Y * f[5]) * Z;
+                }
+                put_g<PREC, KR>(row, j, w * fq);
+            }
+        }
+        // zero K padding up to a whole number of k-steps
+        constexpr int KFILL = PREC == PREC_BF16X3 ? 3 * KR : KR;
+#pragma unroll 1
+        for (int k = KFILL + grp; k < KS * kstep(PREC); k += 4) row[k] = g_t(0);
+        wave_sync();
+
+        acc_t acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+        if constexpr (C::RREG) {
+            // fragments in registers: straight-line code (constant indices)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const frag_t a = load_afrag<PREC>(gt, ROW, lane, s);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma<PREC>(a, rreg[t][s], acc[t]);
+            }
+        } else {
+            // fragments through the caches, the next k-step's loads issued
+            // before this k-step's products
+            frag_t bc[NT], bn[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bc[t] = gload(rf + t * KS * 64 + lane);
+#pragma unroll 1
+            for (int s = 0; s < KS; ++s) {
+                const int sn = s + 1 < KS ? s + 1 : s;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) bn[t] = gload(rf + (t * KS + sn) * 64 + lane);
+                const frag_t a = load_afrag<PREC>(gt, ROW, lane, s);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma<PREC>(a, bc[t], acc[t]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) bc[t] = bn[t];
+            }
+        }
+        wave_sync();  // every G read is done: the staging area reuses the rows
+
+        // two halves of 8 cells, each written to LDS in full (both triangles)
+        // and copied out as contiguous 16-byte stores
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t c0 = base + 8 * h;
+            if (c0 >= A.ncells) break;  // wave-uniform
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (t * 16 + col >= NU) continue;
+                const int oab = ua[t] * NS + ub[t], oba = ub[t] * NS + ua[t];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = acc_row<PREC>(lane, v);
+                    if ((r >> 3) != h) continue;
+                    const out_t xv = (out_t)acc[t][v];
+                    st[(r & 7) * NN + oab] = xv;
+                    st[(r & 7) * NN + oba] = xv;
+                }
+            }
+            wave_sync();
+            const int nc = A.ncells - c0 < 8 ? (int)(A.ncells - c0) : 8;
+            const int nelem = nc * NN;
+            constexpr int PER16 = 16 / (int)sizeof(out_t);
+            const int nvec = nelem / PER16;
+            const u32x4p* s4 = reinterpret_cast<const u32x4p*>(st);
+            out_t* dst = out + c0 * NN;
+            u32x4p* d4 = reinterpret_cast<u32x4p*>(dst);
+            for (int i = lane; i < nvec; i += 64) gstore_nt(&d4[i], s4[i]);
+            for (int i = nvec * PER16 + lane; i < nelem; i += 64) gstore(&dst[i], st[i]);
+            wave_sync();
+        }
+    }
+}
+
+}  // namespace dev
+
+namespace {
+
+using ld = long double;
+
+// Reference products per point (no weights; the weights are in G), in the
+// device's column order k = q JQ + j.
+bool prism_reference(int form, int p, int quad, RefTensor& R, std::vector<double>& qtab) {
+    PrismTables t;
+    if (!t.init(p, quad)) return false;
+    const int n = t.n, nq = t.nq, NN = n * n;
+    const int JQ = dev::prism_jq(form == COFFEE_MASS ? dev::F_MASS : (form == COFFEE_HELMHOLTZ ? dev::F_HELM
+                                                                                                : dev::F_DIFF));
+    R.NS = n;
+    R.KR = nq * JQ;
+    R.R.assign((size_t)R.KR * NN, 0.0L);
+    auto ph = [&](int k, int a) -> ld { return t.phi[(size_t)k * n + a]; };
+    auto dph = [&](int al, int k, int a) -> ld { return t.dphi[((size_t)al * nq + k) * n + a]; };
+    for (int k = 0; k < nq; ++k) {
+        int j = k * JQ;
+        if (form != COFFEE_MASS) {
+            for (int al = 0; al < 3; ++al)
+                for (int be = al; be < 3; ++be, ++j)
+                    for (int a = 0; a < n; ++a)
+                        for (int b = 0; b < n; ++b) {
+                            ld v = dph(al, k, a) * dph(be, k, b);
+                            if (al != be) v += dph(be, k, a) * dph(al, k, b);
+                            R.R[(size_t)j * NN + a * n + b] = v;
+                        }
+        }
+        if (form != COFFEE_DIFFUSION)
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) R.R[(size_t)j * NN + a * n + b] = ph(k, a) * ph(k, b);
+    }
+    qtab.resize(4 * (size_t)nq);
+    for (int k = 0; k < nq; ++k) {
+        for (int i = 0; i < 3; ++i) qtab[4 * k + i] = (double)t.X[3 * k + i];
+        qtab[4 * k + 3] = (double)t.W[k];
+    }
+    return true;
+}
+
+struct PrismTable {
+    void* frag = nullptr;
+    double* qtab = nullptr;
+};
+
+std::mutex g_prism_mu;
+std::map<std::tuple<int, int, int, int, int>, PrismTable> g_prism_tabs;  // (dev, form, p, quad, prec)
+
+coffee_status prism_table(int dev, int form, int p, int quad, int prec, PrismTable* out) {
+    std::lock_guard<std::mutex> lk(g_prism_mu);
+    auto key = std::make_tuple(dev, form, p, quad, prec);
+    auto it = g_prism_tabs.find(key);
+    if (it != g_prism_tabs.end()) {
+        *out = it->second;
+        return COFFEE_OK;
+    }
+    RefTensor R;
+    std::vector<double> qtab;
+    if (!prism_reference(form, p, quad, R, qtab)) return COFFEE_E_INVALID_ARG;
+    const std::vector<char> frag = pack_fragments(R, prec, true, 0);
+    PrismTable t;
+    if (hipMalloc(&t.frag, frag.size()) != hipSuccess) return COFFEE_E_NOMEM;
+    if (hipMalloc((void**)&t.qtab, qtab.size() * sizeof(double)) != hipSuccess) {
+        (void)hipFree(t.frag);
+        return COFFEE_E_NOMEM;
+    }
+    if (hipMemcpy(t.frag, frag.data(), frag.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t.qtab, qtab.data(), qtab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(t.frag);
+        (void)hipFree(t.qtab);
+        return COFFEE_E_HIP;
+    }
+    g_prism_tabs[key] = t;
+    *out = t;
+    return COFFEE_OK;
+}
+
+template <int FORM, int P, int FD, int PREC, int NQ>
+hipError_t launch_prism(const dev::PrismArgs& a, hipStream_t s, int dev_id) {
+    using C = dev::PrismCfg<FORM, P, FD, PREC, NQ>;
+    const void* kern = reinterpret_cast<const void*>(&dev::k_prism<FORM, P, FD, PREC, NQ>);
+    static const hipError_t attr =
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+    if (attr != hipSuccess) return attr;
+    const int64_t wgs_needed = (a.ntiles + C::WAVES - 1) / C::WAVES;
+    const int grid = grid_for(dev_id, kern, C::WAVES * 64, C::LDS_BYTES, wgs_needed, 1);
+    hipLaunchKernelGGL((dev::k_prism<FORM, P, FD, PREC, NQ>), dim3(grid), dim3(C::WAVES * 64), C::LDS_BYTES, s, a);
+    return hipGetLastError();
+}
+
+template <int FORM, int P, int FD, int NQ>
+hipError_t launch_prism_prec(int prec, const dev::PrismArgs& a, hipStream_t s, int dev_id) {
+    if (prec == COFFEE_FP64) return launch_prism<FORM, P, FD, dev::PREC_F64, NQ>(a, s, dev_id);
+    if (prec == COFFEE_FP32) return launch_prism<FORM, P, FD, dev::PREC_F32, NQ>(a, s, dev_id);
+    return launch_prism<FORM, P, FD, dev::PREC_BF16X3, NQ>(a, s, dev_id);
+}
+
+template <int P, int NQ>
+hipError_t launch_prism_form(int form, int fd, int prec, const dev::PrismArgs& a, hipStream_t s, int dev_id) {
+    using namespace dev;
+    if (form == COFFEE_DIFFUSION) return launch_prism_prec<F_DIFF, P, 0, NQ>(prec, a, s, dev_id);
+    if (form == COFFEE_MASS)
+        return fd ? launch_prism_prec<F_MASS, P, 1, NQ>(prec, a, s, dev_id)
+                  : launch_prism_prec<F_MASS, P, 0, NQ>(prec, a, s, dev_id);
+    return fd ? launch_prism_prec<F_HELM, P, 1, NQ>(prec, a, s, dev_id)
+              : launch_prism_prec<F_HELM, P, 0, NQ>(prec, a, s, dev_id);
+}
+
+}  // namespace
+
+// Prism entry of coffee_assemble: arguments already validated (form mass,
+// Helmholtz or diffusion; field none or degree 1 scalar).
+coffee_status assemble_prism(int form, int degree, int quad, int precision, const double* coords,
+                             const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, int ncoeff,
+                             const double* constants, int nconst, void* out, void* hip_stream) {
+    // compiled: the default rule (q = 2p) at degree 1 (8 points) and 2 (27 points)
+    if (degree < 1 || degree > 2 || quad != 2 * degree) return COFFEE_E_UNSUPPORTED;
+    if (ncells == 0) return COFFEE_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return COFFEE_E_HIP;
+    PrismTable t;
+    coffee_status st = prism_table(dev, form, degree, quad, precision, &t);
+    if (st != COFFEE_OK) return st;
+    dev::PrismArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.coords = coords;
+    a.c2v = c2v;
+    a.ncells = ncells;
+    if (ncoeff >= 1) a.f = dev::FieldArg{coeffs[0].values, coeffs[0].cell_to_dof};
+    a.kdt = (nconst > 0 ? constants[0] : 1.0) * (nconst > 1 ? constants[1] : 1.0);
+    a.qtab = t.qtab;
+    a.rfrag = t.frag;
+    a.out = out;
+    a.ntiles = (ncells + 15) / 16;
+    const int fd = ncoeff >= 1 ? 1 : 0;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const hipError_t e = degree == 1 ? launch_prism_form<1, 8>(form, fd, precision, a, s, dev)
+                                     : launch_prism_form<2, 27>(form, fd, precision, a, s, dev);
+    return e == hipSuccess ? COFFEE_OK : COFFEE_E_HIP;
+}
+
+void free_prism_tables() {
+    std::lock_guard<std::mutex> lk(g_prism_mu);
+    for (auto& kv : g_prism_tabs) {
+        (void)hipSetDevice(std::get<0>(kv.first));
+        (void)hipFree(kv.second.frag);
+        (void)hipFree(kv.second.qtab);
+    }
+    g_prism_tabs.clear();
+}
+
+}  // namespace coffee

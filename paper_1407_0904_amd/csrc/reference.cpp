@@ -14,6 +14,7 @@
 // Tensor order per form (the device builds G in the same order):
 //   MASS        [r]                       r over field dofs (one tensor if no field)
 //   HELMHOLTZ   [(a,b) a<=b] + mass part  stiffness pairs, symmetric sum for a<b
+//   DIFFUSION   [(a,b) a<=b]              the Helmholtz stiffness pairs alone
 //   ELASTICITY  [(r, a, b)]               r over Lame dofs (one if constants)
 //   BURGERS     [M] [(a,b) a<=b] [C(r,a)] [E(r,a)]
 //       M = W phi_a phi_b, C(r,a) = W psi_r phi_a d_a phi_b, E(r,a) = W d_a psi_r phi_a phi_b
@@ -52,6 +53,7 @@ bool build_reference(int form, int dim, int p, int q, int fdeg, RefTensor& out) 
     switch (form) {
         case COFFEE_MASS: KR = nf; break;
         case COFFEE_HELMHOLTZ: KR = npair + nf; break;
+        case COFFEE_DIFFUSION: KR = npair; break;
         case COFFEE_ELASTICITY: KR = nf * dim * dim; break;
         case COFFEE_BURGERS: KR = 1 + npair + 2 * nf * dim; break;
         default: return false;
@@ -66,7 +68,7 @@ bool build_reference(int form, int dim, int p, int q, int fdeg, RefTensor& out) 
             for (int b = 0; b < n; ++b) {
                 const ld pp = phi(k, a) * phi(k, b);
                 int t = 0;
-                if (form == COFFEE_HELMHOLTZ || form == COFFEE_BURGERS) {
+                if (form == COFFEE_HELMHOLTZ || form == COFFEE_BURGERS || form == COFFEE_DIFFUSION) {
                     if (form == COFFEE_BURGERS) R(t++, a, b) += w * pp;
                     for (int s = 0; s < npair; ++s) {
                         int al = pr[s][0], be = pr[s][1];

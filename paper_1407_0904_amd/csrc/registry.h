@@ -23,9 +23,11 @@ struct LinEntry {
     int cells_per_chunk;  // LinArgs::nchunks = ceil(ncells / cells_per_chunk)
 };
 
-// Mass and Helmholtz are symmetric single-block forms and use the symmetric
+// Mass, Helmholtz and diffusion are symmetric single-block forms and use the symmetric
 // engine (scalar.hpp); the vector forms use the panel engine (vector.hpp).
-constexpr bool uses_scalar_engine(int form) { return form == dev::F_MASS || form == dev::F_HELM; }
+constexpr bool uses_scalar_engine(int form) {
+    return form == dev::F_MASS || form == dev::F_HELM || form == dev::F_DIFF;
+}
 
 template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 const void* kernel_of() {
@@ -91,6 +93,7 @@ void register_helmholtz_tri(std::vector<LinEntry>& v);
 void register_helmholtz_tet(std::vector<LinEntry>& v);
 void register_elasticity(std::vector<LinEntry>& v);
 void register_burgers(std::vector<LinEntry>& v);
+void register_diffusion(std::vector<LinEntry>& v);
 void register_variants(std::vector<LinEntry>& v);
 
 }  // namespace coffee

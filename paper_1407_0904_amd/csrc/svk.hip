@@ -1051,8 +1051,8 @@ extern "C" coffee_status coffee_assemble_adjoint(int form, int cell, int degree,
                                        constants, nconst, &q, &fd);
     if (st != COFFEE_OK) return st;
     if (deterministic != 0 && deterministic != 1) return COFFEE_E_INVALID_ARG;
-    if (form == COFFEE_SVK_JACOBIAN) return COFFEE_E_UNSUPPORTED;
-    if (form < COFFEE_SVK_ENERGY && ncells > 0 && (!lam || !u)) return COFFEE_E_INVALID_ARG;
+    if (form == COFFEE_SVK_JACOBIAN || cell == COFFEE_PRISM) return COFFEE_E_UNSUPPORTED;
+    if (!is_svk_form(form) && ncells > 0 && (!lam || !u)) return COFFEE_E_INVALID_ARG;
     for (int i = 0; i < ncoeff; ++i)
         if (coeffs[i].ncomp > 3) return COFFEE_E_UNSUPPORTED;
     DetTarget det[3];
@@ -1062,7 +1062,7 @@ extern "C" coffee_status coffee_assemble_adjoint(int form, int cell, int degree,
         st = det_carve(workspace, workspace_bytes, det, ndet);
         if (st != COFFEE_OK) return st;
     }
-    if (form >= COFFEE_SVK_ENERGY)
+    if (is_svk_form(form))
         st = adjoint_svk(form, cell, degree, q, coords, c2v, ncells, coeffs, constants, nconst, lam, seed,
                          grad_coords, grad_coeff_values, cell_value, deterministic ? det : nullptr, hip_stream);
     else
@@ -1076,7 +1076,7 @@ extern "C" coffee_status coffee_assemble_adjoint(int form, int cell, int degree,
 extern "C" int64_t coffee_adjoint_workspace_size(int form, int cell, int degree, int64_t nvert, int64_t ncells,
                                                  const coffee_field* coeffs, int ncoeff) {
     using namespace coffee;
-    if (form < COFFEE_MASS || form > COFFEE_SVK_RESIDUAL) return -1;
+    if (form < COFFEE_MASS || form > COFFEE_DIFFUSION || form == COFFEE_SVK_JACOBIAN) return -1;
     if ((cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) || degree < 1 || degree > kMaxP) return -1;
     if (nvert < 0 || ncells < 0 || ncoeff < 0 || ncoeff > 2 || (ncoeff > 0 && !coeffs)) return -1;
     for (int i = 0; i < ncoeff; ++i)

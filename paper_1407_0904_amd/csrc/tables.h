@@ -39,6 +39,19 @@ struct Tables {
     bool init(int dim, int p, int q);
 };
 
+// A rule and a basis on the reference prism T x [0,1] (T the reference
+// triangle): the triangle rule of `quad` times Gauss-Legendre with
+// m = ceil((q + 1) / 2) points on [0,1], triangle point outermost; the degree-p
+// tensor-product Lagrange basis, local dof a (p + 1) + b for triangle dof a and
+// interval dof b (interval nodes 0, 1, then interior ascending).
+struct PrismTables {
+    int p = 0, n = 0, nq = 0;
+    std::vector<long double> X, W, phi, dphi;  // [nq][3], [nq], [nq][n], [3][nq][n]
+    bool init(int p, int quad);
+};
+int prism_rule_size(int quad);  // -1 if the rule does not exist
+int n_prism(int p);
+
 // Reference tensors of a linear form: the element tensor of every affine cell
 // is A[blk][ab] = sum_k G[blk][k](cell) R[k][ab], exactly (up to rounding) the
 // quadrature sum, because the geometry and the coefficient fields are

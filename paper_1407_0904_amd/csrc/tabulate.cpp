@@ -298,12 +298,125 @@ bool Tables::init(int dim_, int p_, int q_) {
     return true;
 }
 
+int n_prism(int p) { return (p + 1) * (p + 2) / 2 * (p + 1); }
+
+int prism_rule_size(int quad) {
+    const int nt = rule_size(2, quad);
+    return nt <= 0 ? -1 : nt * (((quad & 15) + 2) / 2);
+}
+
+// Degree-p Lagrange basis on [0,1] with nodes 0, 1, 1/p, ..., (p-1)/p, as
+// monomial coefficients from the inverse Vandermonde matrix (as for Basis).
+static bool interval_basis(int p, ld (*coef)[kMaxP + 1]) {
+    const int n = p + 1;
+    ld nodes[kMaxP + 1];
+    nodes[0] = 0.0L;
+    if (p >= 1) nodes[1] = 1.0L;
+    for (int k = 1; k < p; ++k) nodes[k + 1] = (ld)k / p;
+    ld A[kMaxP + 1][2 * (kMaxP + 1)];
+    for (int b = 0; b < n; ++b) {
+        ld v = 1.0L;
+        for (int m = 0; m < n; ++m) { A[b][m] = v; v *= nodes[b]; }
+        for (int m = 0; m < n; ++m) A[b][n + m] = (b == m) ? 1.0L : 0.0L;
+    }
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabsl(A[r][col]) > fabsl(A[piv][col])) piv = r;
+        if (A[piv][col] == 0.0L) return false;
+        if (piv != col)
+            for (int j = 0; j < 2 * n; ++j) { ld t = A[col][j]; A[col][j] = A[piv][j]; A[piv][j] = t; }
+        const ld pv = A[col][col];
+        for (int j = 0; j < 2 * n; ++j) A[col][j] /= pv;
+        for (int r = 0; r < n; ++r) {
+            if (r == col || A[r][col] == 0.0L) continue;
+            const ld f = A[r][col];
+            for (int j = 0; j < 2 * n; ++j) A[r][j] -= f * A[col][j];
+        }
+    }
+    for (int m = 0; m < n; ++m)
+        for (int b = 0; b < n; ++b) coef[m][b] = A[m][n + b];
+    return true;
+}
+
+bool PrismTables::init(int p_, int quad) {
+    p = p_;
+    Basis tb;
+    if (p < 0 || p > kMaxP || !tb.init(2, p)) return false;
+    const int nt = rule_size(2, quad);
+    if (nt <= 0) return false;
+    const int m = ((quad & 15) + 2) / 2;
+    std::vector<ld> Xt(2 * nt), Wt(nt);
+    ld z[16], wz[16];
+    if (!simplex_rule(2, quad, Xt.data(), Wt.data()) || !gauss_jacobi01(m, 0, z, wz)) return false;
+    ld coef[kMaxP + 1][kMaxP + 1];
+    if (!interval_basis(p, coef)) return false;
+    const int nt_dofs = tb.n;
+    n = nt_dofs * (p + 1);
+    nq = nt * m;
+    X.assign(3 * nq, 0.0L);
+    W.assign(nq, 0.0L);
+    phi.assign((size_t)nq * n, 0.0L);
+    dphi.assign((size_t)3 * nq * n, 0.0L);
+    ld tph[kMaxN], tdph[2 * kMaxN];
+    for (int i = 0; i < nt; ++i) {
+        tb.eval(&Xt[2 * i], tph, tdph);
+        for (int j = 0; j < m; ++j) {
+            const int k = i * m + j;
+            X[3 * k] = Xt[2 * i];
+            X[3 * k + 1] = Xt[2 * i + 1];
+            X[3 * k + 2] = z[j];
+            W[k] = Wt[i] * wz[j];
+            ld l[kMaxP + 1], dl[kMaxP + 1];
+            for (int b = 0; b <= p; ++b) {
+                ld v = 0.0L, dv = 0.0L, pw = 1.0L;
+                for (int e = 0; e <= p; ++e) {
+                    v += coef[e][b] * pw;
+                    if (e + 1 <= p) dv += coef[e + 1][b] * (e + 1) * pw;
+                    pw *= z[j];
+                }
+                l[b] = v;
+                dl[b] = dv;
+            }
+            for (int a = 0; a < nt_dofs; ++a)
+                for (int b = 0; b <= p; ++b) {
+                    const int r = a * (p + 1) + b;
+                    phi[(size_t)k * n + r] = tph[a] * l[b];
+                    dphi[((size_t)0 * nq + k) * n + r] = tdph[a] * l[b];
+                    dphi[((size_t)1 * nq + k) * n + r] = tdph[nt_dofs + a] * l[b];
+                    dphi[((size_t)2 * nq + k) * n + r] = tph[a] * dl[b];
+                }
+        }
+    }
+    return true;
+}
+
 }  // namespace coffee
 
 extern "C" coffee_status coffee_tabulate(int cell, int degree, int quad_degree, int* nq, int* ndof,
                                          double* points, double* weights, double* basis, double* dbasis) {
-    if ((cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON) || !nq || !ndof) return COFFEE_E_INVALID_ARG;
+    if ((cell != COFFEE_TRIANGLE && cell != COFFEE_TETRAHEDRON && cell != COFFEE_PRISM) || !nq || !ndof)
+        return COFFEE_E_INVALID_ARG;
     if (degree < 0 || degree > coffee::kMaxP || quad_degree < 0) return COFFEE_E_INVALID_ARG;
+    if (cell == COFFEE_PRISM) {
+        const int nqp = coffee::prism_rule_size(quad_degree);
+        if (nqp <= 0) return COFFEE_E_INVALID_ARG;
+        *nq = nqp;
+        *ndof = coffee::n_prism(degree);
+        if (!points && !weights && !basis && !dbasis) return COFFEE_OK;
+        coffee::PrismTables t;
+        if (!t.init(degree, quad_degree)) return COFFEE_E_INVALID_ARG;
+        for (int k = 0; k < t.nq; ++k) {
+            if (points)
+                for (int j = 0; j < 3; ++j) points[k * 3 + j] = (double)t.X[k * 3 + j];
+            if (weights) weights[k] = (double)t.W[k];
+            if (basis)
+                for (int a = 0; a < t.n; ++a) basis[(size_t)k * t.n + a] = (double)t.phi[(size_t)k * t.n + a];
+        }
+        if (dbasis)
+            for (size_t i = 0; i < t.dphi.size(); ++i) dbasis[i] = (double)t.dphi[i];
+        return COFFEE_OK;
+    }
     const int dim = cell;
     if (coffee::rule_size(dim, quad_degree) <= 0) return COFFEE_E_INVALID_ARG;
     *nq = coffee::rule_size(dim, quad_degree);

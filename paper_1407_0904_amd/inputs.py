@@ -210,7 +210,7 @@ class Field:
 @dataclass
 class Workload:
     name: str
-    form: str          # mass | helmholtz | elasticity | burgers | svk_energy | svk_residual | svk_jacobian
+    form: str          # mass | helmholtz | diffusion | elasticity | burgers | svk_energy | svk_residual | svk_jacobian
     mesh: Mesh
     degree: int
     quad_degree: int
@@ -245,12 +245,14 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> Worklo
     elasticity_p2_tet  vector P2 elasticity, mu, lambda P1 ~ U[1,10], q=4, adjoint weights ~ N(0,1) (n=48)
     svk_p1_tet / svk_p2_tet  St Venant-Kirchhoff, u ~ N(0, 0.01) per component, mu = lambda = 1 (n=32)
     burgers_p1_tet / burgers_p2_tet  Burgers Jacobian, w ~ U[-1,1], nu = 1/dt = 1, q = 2p+1 (n=48)
+    helmholtz_p1_prism  Helmholtz P1 on warped prisms, f P1 ~ U[0.5,1.5], jitter 10%, q=2 (n=64: 524,288 cells)
+    diffusion_p2_prism  diffusion P2 on warped prisms, kappa = 1, dt = 1, jitter 10%, q=4 (n=64)
     mass_pK_tri / helmholtz_pK_tet etc. are built by mixed_batch().
     """
     defaults = {
         "helmholtz_p1_tri": 64, "helmholtz_p2_tet": 64, "elasticity_p2_tet": 48,
         "elasticity_p1_tet": 48, "svk_p1_tet": 32, "svk_p2_tet": 32,
-        "burgers_p1_tet": 48, "burgers_p2_tet": 48,
+        "burgers_p1_tet": 48, "burgers_p2_tet": 48, "helmholtz_p1_prism": 64, "diffusion_p2_prism": 64,
     }
     if name not in defaults:
         raise KeyError(name)
@@ -283,6 +285,13 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> Worklo
         else:
             u = _p2_field(mesh, normal, rng, 3)
         return Workload(name, "svk_jacobian", mesh, p, 2 * p, [u], [1.0, 1.0])
+    if name == "helmholtz_p1_prism":
+        mesh = make_prism_mesh(n, 0.10, rng)
+        f = _p1_field(mesh, rng.uniform(0.5, 1.5, size=mesh.nvert), 1)
+        return Workload(name, "helmholtz", mesh, 1, 2, [f])
+    if name == "diffusion_p2_prism":
+        mesh = make_prism_mesh(n, 0.10, rng)
+        return Workload(name, "diffusion", mesh, 2, 4, [], [1.0, 1.0])
     if name in ("burgers_p1_tet", "burgers_p2_tet"):
         p = 1 if name == "burgers_p1_tet" else 2
         mesh = make_mesh(3, n, 0.10, rng)

@@ -39,7 +39,7 @@ def cell_rel_err(got: np.ndarray, ref: np.ndarray) -> float:
 def assemble_gpu(form, mesh, degree, fields, constants=(), quad_degree=-1, precision="fp64"):
     from paper_1407_0904_amd import coffee
     coords, c2v, dfs = to_dev(mesh, fields)
-    out = coffee.coffee_assemble(form, mesh.d, degree, coords, c2v, coeffs=dfs, constants=constants,
+    out = coffee.coffee_assemble(form, mesh.cell, degree, coords, c2v, coeffs=dfs, constants=constants,
                                  quad_degree=quad_degree, precision=precision)
     torch.cuda.synchronize()
     return out

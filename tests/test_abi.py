@@ -65,12 +65,49 @@ def test_validation_before_any_hip_call(lib):
     assert _assemble(lib, form=2, coords=dummy, c2v=dummy, out=dummy) == 1
     # Burgers needs one vector field
     assert _assemble(lib, form=3, coords=dummy, c2v=dummy, out=dummy) == 1
+    # prisms (cell 6): vector forms, degree 3 and a non-default rule are outside the compiled set;
+    # diffusion (form 7) takes no field
+    assert _assemble(lib, form=2, cell=6, coords=dummy, c2v=dummy, out=dummy) == 2
+    assert _assemble(lib, form=1, cell=6, degree=3, coords=dummy, c2v=dummy, out=dummy) == 2
+    assert _assemble(lib, form=7, cell=6, q=3, coords=dummy, c2v=dummy, out=dummy) == 2
+    assert _assemble(lib, form=8, coords=dummy, c2v=dummy, out=dummy) == 1
 
 
 def test_tensor_dims(lib):
     f = lib.coffee_tensor_dim
     assert f(1, 2, 1) == 3 and f(1, 3, 2) == 10 and f(2, 3, 2) == 30 and f(3, 3, 1) == 12
     assert f(0, 3, 4) == 35 and f(4, 3, 2) == 0 and f(6, 3, 2) == 30 and f(9, 3, 2) == -1
+    # diffusion (7) is scalar; prisms (6): 6, 18, 40, 75 dofs, scalar forms only
+    assert f(7, 2, 3) == 10 and f(7, 3, 2) == 10
+    assert [f(1, 6, p) for p in (1, 2, 3, 4)] == [6, 18, 40, 75] and f(7, 6, 2) == 18 and f(2, 6, 1) == -1
+
+
+def test_diffusion_instances_registered(lib):
+    """Every diffusion key (triangles and tetrahedra, P1-P4, no field) has a
+    kernel in every precision (a registry lookup, no HIP call)."""
+    f = lib.coffee_has_variant
+    for d in (2, 3):
+        for p in (1, 2, 3, 4):
+            for prec in (0, 1, 2):
+                assert f(7, d, p, 0, prec, 0) == 1, (d, p, prec)
+    assert f(7, 3, 2, 1, 0, 0) == 0  # no field-carrying diffusion
+
+
+@pytest.mark.parametrize("p,q", [(1, 2), (2, 4), (3, 6), (4, 8), (2, 2 + 16), (0, 3)])
+def test_prism_tabulate_matches_oracle(lib, oracle, p, q):
+    """Library prism tables (Golub-Welsch rules, Vandermonde bases) equal the oracle's."""
+    nq, nd = C.c_int(), C.c_int()
+    tab = lib.coffee_tabulate
+    tab.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)] + [C.c_void_p] * 4
+    assert tab(6, p, q, C.byref(nq), C.byref(nd), None, None, None, None) == 0
+    X = np.zeros((nq.value, 3)); W = np.zeros(nq.value); B = np.zeros((nq.value, nd.value))
+    D = np.zeros((3, nq.value, nd.value))
+    assert tab(6, p, q, C.byref(nq), C.byref(nd), X.ctypes.data, W.ctypes.data, B.ctypes.data, D.ctypes.data) == 0
+    Xo, Wo, Bo, Do = oracle.tabulate(6, p, q)
+    np.testing.assert_allclose(X, Xo, atol=1e-15)
+    np.testing.assert_allclose(W, Wo, rtol=1e-14)
+    np.testing.assert_allclose(B, Bo, atol=2e-14)
+    np.testing.assert_allclose(D, Do, atol=1e-13)
 
 
 @pytest.mark.parametrize("d,p,q", [(2, 1, 2), (2, 4, 8), (3, 2, 4), (3, 3, 6), (3, 4, 8), (2, 2, 5), (3, 0, 3)])
