@@ -48,6 +48,8 @@ WORKLOADS = {
     "elasticity_p2_tet": "elasticity vector P2 tetrahedra, 48^3 x 6 cells, mu, lambda P1 ~ U[1,10], q = 4",
     "burgers_p2_tet": "Burgers Jacobian vector P2 tetrahedra, 48^3 x 6 cells, w P2 ~ U[-1,1], q = 5",
     "burgers_p1_tet": "Burgers Jacobian vector P1 tetrahedra, 48^3 x 6 cells, w P1 ~ U[-1,1], q = 3",
+    "helmholtz_p1_prism": "Helmholtz P1 warped prisms, 64^2 x 2 x 64 cells, f P1 ~ U[0.5,1.5], jitter 10%, q = 2",
+    "diffusion_p2_prism": "diffusion P2 warped prisms, 64^2 x 2 x 64 cells, kappa = dt = 1, jitter 10%, q = 4",
 }
 
 log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
@@ -110,6 +112,20 @@ def svk_work(d: int, p: int, form: str, prec: str) -> dict:
             "valu_f32": nq * (pt + P + 4 * D ** 3 + 2 * D * D) + nb * kj * 10}
 
 
+def prism_work(w, prec: str) -> dict:
+    """Prisms (non-affine): per point, J, det J, K = J^-1, K K^T and the
+    mass factor on the FP64 vector units (about 150 flops), then the
+    contraction over K = nq x (terms per point) for the n(n+1)/2 unique
+    entries on the matrix cores of the precision."""
+    p, form = w.degree, w.form
+    ns = (p + 1) * (p + 2) // 2 * (p + 1)
+    m = (w.quad_degree + 2) // 2
+    nq = m * m * m
+    jq = {"mass": 1, "helmholtz": 7, "diffusion": 6}[form]
+    mm = {"fp64": "mfma_f64", "fp32": "mfma_f32", "bf16x3": "mfma_bf16x3"}[prec]
+    return {mm: 2.0 * nq * jq * ns * (ns + 1) / 2, "valu_f64": 150.0 * nq}
+
+
 def work_model(w, prec: str) -> dict:
     """Flops per cell of the formulation each kernel implements, by unit.
 
@@ -121,6 +137,8 @@ def work_model(w, prec: str) -> dict:
     d, p, form = w.mesh.d, w.degree, w.form
     if form.startswith("svk"):
         return svk_work(d, p, form, prec)
+    if w.mesh.cell == 6:
+        return prism_work(w, prec)
     ns = n_scalar(d, p)
     nd = d * (d + 1) // 2
     fd = w.fields[0].degree if w.fields else 0
@@ -233,9 +251,9 @@ def measure_forward(ctx, w, prec, sample_n=300, seed=3, tag=None):
     torch, cf = ctx.torch, ctx.cf
     coords, c2v, fields = ctx.upload(w)
     E = w.mesh.ncells
-    shape = cf.output_shape(w.form, E, w.mesh.d, w.degree)
+    shape = cf.output_shape(w.form, E, w.mesh.cell, w.degree)
     out = torch.empty(shape, dtype=torch.float64 if prec == "fp64" else torch.float32, device=ctx.dev)
-    fn = cf.PreparedAssemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields, constants=w.constants,
+    fn = cf.PreparedAssemble(w.form, w.mesh.cell, w.degree, coords, c2v, coeffs=fields, constants=w.constants,
                              quad_degree=w.quad_degree, precision=prec, out=out)
     ms, per = time_gpu(fn, ctx.steps, ctx.warmup)
     sample = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(seed).integers(0, E, sample_n)]))
@@ -433,7 +451,7 @@ def forms_section(ctx):
                 res.append(measure_forward(ctx, w, prec, sample_n=150))
         w.form = "svk_energy"
         res.append(measure_adjoint(ctx, w, name))
-    for name in ("burgers_p1_tet", "burgers_p2_tet"):
+    for name in ("burgers_p1_tet", "burgers_p2_tet", "helmholtz_p1_prism", "diffusion_p2_prism"):
         w = I.workload(name)
         for prec in ("fp64", "fp32", "bf16x3"):
             res.append(measure_forward(ctx, w, prec, sample_n=150))

@@ -30,6 +30,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "library.h"
@@ -120,8 +121,44 @@ __device__ inline void put_g(typename PrecT<PREC>::gtype* row, int k, double g) 
     }
 }
 
+// The gathers of one cell in two dependent stages (indices, then values), so
+// that the tile loop can issue them ahead of use.
+struct PrismIdx {
+    int v[6];
+    int fm[6];
+};
+template <int FD>
+struct PrismRaw {
+    double x[6][3];
+    double f[FD > 0 ? 6 : 1];
+};
+
+template <int FD>
+__device__ inline void prism_idx(const PrismArgs& A, int64_t cell, PrismIdx& ix) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) ix.v[v] = gload_nt(A.c2v + cell * 6 + v);
+    if constexpr (FD > 0) {
+        if (A.f.map) {
+#pragma unroll
+            for (int v = 0; v < 6; ++v) ix.fm[v] = gload_nt(A.f.map + cell * 6 + v);
+        }
+    }
+}
+
+template <int FD>
+__device__ inline void prism_raw(const PrismArgs& A, int64_t cell, const PrismIdx& ix, PrismRaw<FD>& r) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r.x[v][i] = gload(A.coords + (int64_t)ix.v[v] * 3 + i);
+    if constexpr (FD > 0) {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) r.f[v] = gload(A.f.values + (A.f.map ? (int64_t)ix.fm[v] : cell * 6 + v));
+    }
+}
+
 template <int FORM, int P, int FD, int PREC, int NQ>
-__global__ __launch_bounds__(256) void k_prism(PrismArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_prism(PrismArgs A) {
     using C = PrismCfg<FORM, P, FD, PREC, NQ>;
     using g_t = typename C::g_t;
     using frag_t = typename C::frag_t;
@@ -154,42 +191,89 @@ __global__ __launch_bounds__(256) void k_prism(PrismArgs A) {
             for (int s = 0; s < KS; ++s) rreg[t][s] = gload(rf + (t * KS + s) * 64 + lane);
     }
 
-    const int64_t stride = (int64_t)gridDim.x * C::WAVES;
-    for (int64_t tile = (int64_t)blockIdx.x * C::WAVES + wave; tile < A.ntiles; tile += stride) {
-        const int64_t base = tile * 16;
-        const int64_t cell = base + col;
-        const bool valid = cell < A.ncells;
-        const int64_t cc = valid ? cell : A.ncells - 1;
+    // the rule's points and weights, once per workgroup
+    __shared__ double sq[NQ * 4];
+    for (int i = threadIdx.x; i < NQ * 4; i += blockDim.x) sq[i] = gload(A.qtab + i);
+    __syncthreads();
 
-        // gather: six vertices (each base vertex at the bottom, then the top)
-        double x[6][3], f[6];
+    // Persistent loop over 16-cell tiles, software-pipelined at degree 1:
+    // while tile i is contracted and stored, the vertices and field values of
+    // tile i + 1 and the indices of tile i + 2 are in flight (issued before
+    // this tile's stores, which share the in-order memory counter with them).
+    const int64_t stride = (int64_t)gridDim.x * C::WAVES;
+    int64_t tile = (int64_t)blockIdx.x * C::WAVES + wave;
+    if (tile >= A.ntiles) return;  // wave-uniform; no workgroup barrier follows
+    auto clamp = [&](int64_t t) -> int64_t {
+        const int64_t c = (t < A.ntiles ? t : tile) * 16 + col;
+        return c < A.ncells ? c : A.ncells - 1;
+    };
+    // degree 1 prefetches (short contraction, gather latency dominates); at
+    // degree 2 the contraction hides it and the registers go to occupancy
+    constexpr bool PIPE = P == 1;
+    PrismIdx ix;
+    PrismRaw<FD> raw;
+    if constexpr (PIPE) {
+        prism_idx<FD>(A, clamp(tile), ix);
+        prism_raw<FD>(A, clamp(tile), ix, raw);
+        prism_idx<FD>(A, clamp(tile + stride), ix);
+        // Complete the prologue's loads here (no store is outstanding yet):
+        // the loop's first wait then merges with an empty queue, and the
+        // waits inside the loop can leave this tile's stores in flight.
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            const int64_t g = gload(A.c2v + cc * 6 + v);
+            asm volatile("" ::"v"(ix.v[v]));
+            if constexpr (FD > 0) asm volatile("" ::"v"(ix.fm[v]), "v"(raw.f[v]));
 #pragma unroll
-            for (int i = 0; i < 3; ++i) x[v][i] = gload(A.coords + g * 3 + i);
+            for (int i = 0; i < 3; ++i) asm volatile("" ::"v"(raw.x[v][i]));
         }
-        if constexpr (FD > 0) {
+    }
+    // One tile. FULL: all 16 cells exist, so the stores have compile-time counts
+    // and the next tile's waits need not drain them.
+    auto tile_body = [&](auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        const int64_t base = tile * 16;
+        const bool valid = FULL || base + col < A.ncells;
+        if constexpr (!PIPE) {
+            prism_idx<FD>(A, clamp(tile), ix);
+            prism_raw<FD>(A, clamp(tile), ix, raw);
+        }
+
+        // per-cell edge vectors of the map (bottom and top triangle edges from
+        // vertex t0, vertical edges)
+        double e[7][3];
 #pragma unroll
-            for (int v = 0; v < 6; ++v) {
-                const int64_t src = A.f.map ? (int64_t)gload(A.f.map + cc * 6 + v) : cc * 6 + v;
-                f[v] = gload(A.f.values + src);
-            }
+        for (int i = 0; i < 3; ++i) {
+            e[0][i] = raw.x[2][i] - raw.x[0][i];
+            e[1][i] = raw.x[3][i] - raw.x[1][i];
+            e[2][i] = raw.x[4][i] - raw.x[0][i];
+            e[3][i] = raw.x[5][i] - raw.x[1][i];
+            e[4][i] = raw.x[1][i] - raw.x[0][i];
+            e[5][i] = raw.x[3][i] - raw.x[2][i];
+            e[6][i] = raw.x[5][i] - raw.x[4][i];
+        }
+        double f[6];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) f[v] = FD > 0 ? raw.f[v] : 0.0;
+        if constexpr (PIPE) {
+            // next tile's values (indices loaded one tile ago), then the indices two ahead
+            prism_raw<FD>(A, clamp(tile + stride), ix, raw);
+            prism_idx<FD>(A, clamp(tile + 2 * stride), ix);
         }
 
         // G entries of this lane's points q = grp, grp + 4, ...
         g_t* row = gt + col * ROW;
-#pragma unroll 1
-        for (int q = grp; q < NQ; q += 4) {
-            const double X = gload(A.qtab + 4 * q), Y = gload(A.qtab + 4 * q + 1);
-            const double Z = gload(A.qtab + 4 * q + 2), W = gload(A.qtab + 4 * q + 3);
+#pragma unroll
+        for (int it = 0; it < (NQ + 3) / 4; ++it) {
+            const int q = grp + 4 * it;
+            if (q >= NQ) break;
+            const double X = sq[4 * q], Y = sq[4 * q + 1], Z = sq[4 * q + 2], W = sq[4 * q + 3];
             const double zb = 1.0 - Z, l0 = 1.0 - X - Y;
             double J[3][3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                J[i][0] = zb * (x[2][i] - x[0][i]) + Z * (x[3][i] - x[1][i]);
-                J[i][1] = zb * (x[4][i] - x[0][i]) + Z * (x[5][i] - x[1][i]);
-                J[i][2] = l0 * (x[1][i] - x[0][i]) + X * (x[3][i] - x[2][i]) + Y * (x[5][i] - x[4][i]);
+                J[i][0] = zb * e[0][i] + Z * e[1][i];
+                J[i][1] = zb * e[2][i] + Z * e[3][i];
+                J[i][2] = l0 * e[4][i] + X * e[5][i] + Y * e[6][i];
             }
             double K[3][3], adet;
             prism_inverse(J, K, adet);
@@ -224,13 +308,19 @@ __global__ __launch_bounds__(256) void k_prism(PrismArgs A) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
         if constexpr (C::RREG) {
-            // fragments in registers: straight-line code (constant indices)
+            // fragments in registers: straight-line code (constant indices);
+            // every G fragment is read from LDS before the first product, so
+            // the reads overlap one another instead of each MFMA pair waiting
+            // for its own read
+            frag_t afr[KS];
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const frag_t a = load_afrag<PREC>(gt, ROW, lane, s);
+            for (int s = 0; s < KS; ++s) afr[s] = load_afrag<PREC>(gt, ROW, lane, s);
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] = mfma<PREC>(a, rreg[t][s], acc[t]);
-            }
+            for (int s = 0; s < KS; ++s) asm volatile("" ::"v"(afr[s]));  // one wait for all reads
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = mfma<PREC>(afr[s], rreg[t][s], acc[t]);
         } else {
             // fragments through the caches, the next k-step's loads issued
             // before this k-step's products
@@ -256,7 +346,7 @@ __global__ __launch_bounds__(256) void k_prism(PrismArgs A) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t c0 = base + 8 * h;
-            if (c0 >= A.ncells) break;  // wave-uniform
+            if (!FULL && c0 >= A.ncells) break;  // wave-uniform
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 if (t * 16 + col >= NU) continue;
@@ -271,19 +361,46 @@ __global__ __launch_bounds__(256) void k_prism(PrismArgs A) {
                 }
             }
             wave_sync();
-            const int nc = A.ncells - c0 < 8 ? (int)(A.ncells - c0) : 8;
-            const int nelem = nc * NN;
             constexpr int PER16 = 16 / (int)sizeof(out_t);
-            const int nvec = nelem / PER16;
             const u32x4p* s4 = reinterpret_cast<const u32x4p*>(st);
             out_t* dst = out + c0 * NN;
             u32x4p* d4 = reinterpret_cast<u32x4p*>(dst);
-            for (int i = lane; i < nvec; i += 64) gstore_nt(&d4[i], s4[i]);
-            for (int i = nvec * PER16 + lane; i < nelem; i += 64) gstore(&dst[i], st[i]);
+            if constexpr (FULL) {
+                // 8 NN is a multiple of PER16; groups of four LDS reads, then
+                // their four nontemporal stores. Every lane stores (lanes past
+                // the end repeat the last vector, same address and value), so
+                // no branch hides the store count from the wait counters.
+                constexpr int NV = 8 * NN / PER16;
+                constexpr int PL = (NV + 63) / 64;
+#pragma unroll
+                for (int i0 = 0; i0 < PL; i0 += 4) {
+                    u32x4p tmp[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = (i0 + i) * 64 + lane < NV ? (i0 + i) * 64 + lane : NV - 1;
+                        if (i0 + i < PL) tmp[i] = s4[k];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = (i0 + i) * 64 + lane < NV ? (i0 + i) * 64 + lane : NV - 1;
+                        if (i0 + i < PL) gstore_nt(&d4[k], tmp[i]);
+                    }
+                }
+            } else {
+                const int nc = A.ncells - c0 < 8 ? (int)(A.ncells - c0) : 8;
+                const int nelem = nc * NN;
+                const int nvec = nelem / PER16;
+                for (int i = lane; i < nvec; i += 64) gstore_nt(&d4[i], s4[i]);
+                for (int i = nvec * PER16 + lane; i < nelem; i += 64) gstore(&dst[i], st[i]);
+            }
             wave_sync();
         }
-    }
+    };
+    const int64_t nfull = A.ncells / 16;  // tiles whose 16 cells all exist
+    for (; tile < nfull; tile += stride) tile_body(std::integral_constant<bool, true>());
+    if (tile < A.ntiles) tile_body(std::integral_constant<bool, false>());
 }
+
 
 }  // namespace dev
 
