@@ -447,11 +447,8 @@ __host__ __device__ inline void reverse_G(const CellData<FORM, D, FD>& cd, const
 
 // ---------------------------------------------------------------- precision helpers
 
-__device__ inline u16 bf16_bits_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (u16)(u >> 16);
-}
+// bf16(x), rounded to nearest even: one v_cvt_pk_bf16_f32 on gfx950.
+__device__ inline u16 bf16_bits_rne(float x) { return __builtin_bit_cast(u16, (__bf16)x); }
 __device__ inline float bf16_to_float(u16 h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 template <int PREC> struct PrecT;
