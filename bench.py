@@ -40,7 +40,7 @@ TUNING = os.path.join(ROOT, "paper_1407_0904_amd", "tuning_mi355x.txt")
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by a plain copy of known size (profiles/
 # k_scalar_helmholtz_p2_tet_fp64.md); valid only for the kernel they were taken on.
-TRAFFIC = {("helmholtz_p2_tet", "fp64"): 1432.3e6}
+TRAFFIC = {("helmholtz_p2_tet", "fp64"): 1401.3e6}
 
 WORKLOADS = {
     "helmholtz_p2_tet": "Helmholtz P2 tetrahedra, 64^3 x 6 cells, f P2 ~ U[0.5,1.5], jitter 10%, q = 4",
@@ -48,6 +48,7 @@ WORKLOADS = {
     "elasticity_p2_tet": "elasticity vector P2 tetrahedra, 48^3 x 6 cells, mu, lambda P1 ~ U[1,10], q = 4",
     "burgers_p2_tet": "Burgers Jacobian vector P2 tetrahedra, 48^3 x 6 cells, w P2 ~ U[-1,1], q = 5",
     "burgers_p1_tet": "Burgers Jacobian vector P1 tetrahedra, 48^3 x 6 cells, w P1 ~ U[-1,1], q = 3",
+    "svk_p2_tet": "St Venant-Kirchhoff Jacobian vector P2 tetrahedra, 32^3 x 6 cells, u P2 ~ N(0, 0.01^2), q = 4",
     "helmholtz_p1_prism": "Helmholtz P1 warped prisms, 64^2 x 2 x 64 cells, f P1 ~ U[0.5,1.5], jitter 10%, q = 2",
     "diffusion_p2_prism": "diffusion P2 warped prisms, 64^2 x 2 x 64 cells, kappa = dt = 1, jitter 10%, q = 4",
 }
@@ -496,7 +497,7 @@ def main():
     coords, c2v, fields = ctx.upload(w)
     coffee.coffee_set_launch_options(args.grid_mult)
     E = w.mesh.ncells
-    shape = coffee.output_shape(w.form, E, w.mesh.d, w.degree)
+    shape = coffee.output_shape(w.form, E, w.mesh.cell, w.degree)
     sample = np.unique(np.concatenate([[0, E - 1], np.random.default_rng(3).integers(0, E, 1500)]))
     ref = O.assemble(w.form, w.mesh, w.degree, w.quad_degree, fields=w.fields, constants=w.constants, cells=sample)
     idx = torch.as_tensor(sample, device=dev)
@@ -506,7 +507,7 @@ def main():
                                                              if p != args.precision])
     for prec in precs:
         out = torch.empty(shape, dtype=torch.float64 if prec == "fp64" else torch.float32, device=dev)
-        fn = coffee.PreparedAssemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields,
+        fn = coffee.PreparedAssemble(w.form, w.mesh.cell, w.degree, coords, c2v, coeffs=fields,
                                      constants=w.constants, quad_degree=w.quad_degree, precision=prec, out=out)
         ms, per = time_gpu(fn, args.steps, args.warmup)
         err = cell_rel_err(out[idx].cpu().numpy(), ref)
