@@ -159,7 +159,9 @@ std::vector<char> pack_fragments(const RefTensor& R, int prec, bool sym, int row
 bool rtable_bytes(int form, int dim, int p, int q, int fd, int prec, std::vector<char>& buf) {
     RefTensor R;
     if (!build_reference(form, dim, p, q, fd, R)) return false;
-    const int rpg = dev::vec_rows_per_group(R.NS, dev::vec_group_tiles(form, prec));
+    // the cell-row engine reads plain 16-entry column tiles: one row group
+    const int rpg = uses_elast_engine(form, dim, p, fd, prec) ? R.NS
+                                                              : dev::vec_rows_per_group(R.NS, dev::vec_group_tiles(form, prec));
     buf = pack_fragments(R, prec, uses_scalar_engine(form), rpg);
     return true;
 }

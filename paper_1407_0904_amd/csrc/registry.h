@@ -5,6 +5,7 @@
 
 #include <vector>
 
+#include "elast.hpp"
 #include "linear.hpp"
 #include "scalar.hpp"
 #include "vector.hpp"
@@ -24,15 +25,22 @@ struct LinEntry {
 };
 
 // Mass, Helmholtz and diffusion are symmetric single-block forms and use the symmetric
-// engine (scalar.hpp); the vector forms use the panel engine (vector.hpp).
+// engine (scalar.hpp); elasticity uses the cell-row engine (elast.hpp) where its
+// ring of cell slots fits the LDS, the panel engine (vector.hpp) otherwise, and
+// Burgers the panel engine.
 constexpr bool uses_scalar_engine(int form) {
     return form == dev::F_MASS || form == dev::F_HELM || form == dev::F_DIFF;
+}
+constexpr bool uses_elast_engine(int form, int d, int p, int fd, int prec) {
+    return form == dev::F_ELAST && dev::el_sizes(d, p, fd, prec).fits;
 }
 
 template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 const void* kernel_of() {
     if constexpr (uses_scalar_engine(FORM))
         return reinterpret_cast<const void*>(&dev::k_scalar<FORM, D, P, FD, PREC, VAR>);
+    else if constexpr (uses_elast_engine(FORM, D, P, FD, PREC))
+        return reinterpret_cast<const void*>(&dev::k_elast<D, P, FD, PREC>);
     else
         return reinterpret_cast<const void*>(&dev::k_vector<FORM, D, P, FD, PREC>);
 }
@@ -43,6 +51,13 @@ template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 hipError_t launch_linear(const dev::LinArgs& a, hipStream_t s, int grid) {
     if constexpr (uses_scalar_engine(FORM)) {
         hipLaunchKernelGGL((dev::k_scalar<FORM, D, P, FD, PREC, VAR>), dim3(grid), dim3(256), 0, s, a);
+    } else if constexpr (uses_elast_engine(FORM, D, P, FD, PREC)) {
+        using C = dev::ElCfg<D, P, FD, PREC>;
+        static const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&dev::k_elast<D, P, FD, PREC>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, C::S.lds_bytes);
+        if (attr != hipSuccess) return attr;
+        hipLaunchKernelGGL((dev::k_elast<D, P, FD, PREC>), dim3(grid), dim3(C::WAVES * 64), C::S.lds_bytes, s, a);
     } else {
         using C = dev::VecCfg<FORM, D, P, FD, PREC>;
         static const hipError_t attr = hipFuncSetAttribute(
@@ -60,6 +75,10 @@ LinEntry lin_entry() {
     if constexpr (uses_scalar_engine(FORM)) {
         return LinEntry{FORM, D, P, FD, PREC, VAR, &launch_linear<FORM, D, P, FD, PREC, VAR>,
                         kernel_of<FORM, D, P, FD, PREC, VAR>(), 256, 0, 256};
+    } else if constexpr (uses_elast_engine(FORM, D, P, FD, PREC)) {
+        using C = dev::ElCfg<D, P, FD, PREC>;
+        return LinEntry{FORM, D, P, FD, PREC, 0, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>(),
+                        C::WAVES * 64, C::S.lds_bytes, C::WAVES * 16};
     } else {
         using C = dev::VecCfg<FORM, D, P, FD, PREC>;
         return LinEntry{FORM, D, P, FD, PREC, 0, &launch_linear<FORM, D, P, FD, PREC>, kernel_of<FORM, D, P, FD, PREC>(),
