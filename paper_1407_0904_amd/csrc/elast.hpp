@@ -210,7 +210,6 @@ __device__ __forceinline__ void el_rowtile(const LinArgs& A, const ElWave<D, P, 
     // per accumulator element v: the (cell slot, block) origins of its row's
     // upper block and of the transposed lower block
     int based[4], baset[4];
-    bool diag[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = 16 * m + acc_row<PREC>(lane, v);
@@ -220,7 +219,6 @@ __device__ __forceinline__ void el_rowtile(const LinArgs& A, const ElWave<D, P, 
         const int slot = (ci & (C::RING - 1)) * C::CELLV;
         based[v] = slot + c * NS * N + c2 * NS;
         baset[v] = slot + c2 * NS * N + c * NS;
-        diag[v] = c == c2;
     }
 #pragma unroll
     for (int h = 0; h < C::NCH; ++h) {
@@ -247,8 +245,12 @@ __device__ __forceinline__ void el_rowtile(const LinArgs& A, const ElWave<D, P, 
                 if (t < nt) acc[t] = mfma<PREC>(a, b[t], acc[t]);
         }
         // stage: accumulator (row, entry (a, b)) of upper block (c, c2) of a
-        // cell goes to (c n + a, c2 n + b) and, off the diagonal, to
-        // (c2 n + b, c n + a) of the cell's slot
+        // cell goes to (c n + a, c2 n + b) and to (c2 n + b, c n + a) of the
+        // cell's slot. On a diagonal block (c = c2) the second write lands on
+        // (b, a) of the same block: every entry of it is written once from
+        // (a, b) and once from (b, a), two roundings of the same sum of the
+        // symmetric integrand, and the later write in program order stays
+        // (no branch per row; the result is the same on every run).
 #pragma unroll
         for (int t = 0; t < TCH; ++t) {
             if (t < nt) {
@@ -263,41 +265,35 @@ __device__ __forceinline__ void el_rowtile(const LinArgs& A, const ElWave<D, P, 
                     const out_t x = (out_t)acc[t][v];
                     if (ok) {
                         W.ring[based[v] + od] = x;
-                        if (!diag[v]) W.ring[baset[v] + ot] = x;
+                        W.ring[baset[v] + ot] = x;
                     }
                 }
             }
         }
     }
     wave_sync();
-    // cells [cd0, cd1) of the unit are complete: one contiguous range
+    // cells [cd0, cd1) of the unit are complete: one contiguous range of
+    // the output. Their slots are consecutive except where the ring wraps
+    // (compile-time: chunk WQ of the range is the first one in slot 0).
     constexpr int cd0 = (16 * m) / NB, cd1 = (16 * (m + 1)) / NB;
-    constexpr int NQ = (cd1 - cd0) * C::CPC;
+    constexpr int CPC = C::CPC, NQ = (cd1 - cd0) * CPC;
+    constexpr int s0 = cd0 & (C::RING - 1), WQ = (C::RING - s0) * CPC, WRAP = C::RING * CPC;
     if constexpr (NQ > 0) {
-        const vu32x4* ring16 = reinterpret_cast<const vu32x4*>(W.ring);
-        vu32x4* dst = reinterpret_cast<vu32x4*>(A.out) + (unit_base + cd0) * (int64_t)C::CPC;
-        // chunk q = q0 + lane is chunk `off` of cell cd0 + cl, advanced by 64
-        // chunks per step (incrementally when a cell has at least 64 chunks)
-        int cl = lane / C::CPC, off = lane - (lane / C::CPC) * C::CPC;
+        const vu32x4* rb = reinterpret_cast<const vu32x4*>(W.ring) + s0 * CPC;
+        // a wave-uniform base and 32-bit byte offsets: scalar base addressing
+        char* dst = reinterpret_cast<char*>(uniform_ptr(reinterpret_cast<vu32x4*>(A.out) +
+                                                        (unit_base + cd0) * (int64_t)CPC));
 #pragma unroll
         for (int q0 = 0; q0 < NQ; q0 += 64) {
             const int q = q0 + lane;
-            if constexpr (C::CPC < 64) {
-                cl = q / C::CPC;
-                off = q - cl * C::CPC;
+            int li = q;
+            if constexpr (WQ < NQ) {
+                if (q0 >= WQ) li = q - WRAP;
+                else if (q0 + 64 > WQ) li = q >= WQ ? q - WRAP : q;
             }
-            const bool ok = (q0 + 64 <= NQ || q < NQ) && (FULL || unit_base + cd0 + cl < A.ncells);
-            if (ok) {
-                const vu32x4 x = ring16[((cd0 + cl) & (C::RING - 1)) * C::CPC + off];
-                gstore_nt(dst + q, x);
-            }
-            if constexpr (C::CPC >= 64) {
-                off += 64;
-                if (off >= C::CPC) {
-                    off -= C::CPC;
-                    ++cl;
-                }
-            }
+            bool ok = q0 + 64 <= NQ || q < NQ;
+            if constexpr (!FULL) ok = ok && unit_base + cd0 + q / CPC < A.ncells;
+            if (ok) gstore_nt(reinterpret_cast<vu32x4*>(dst + (uint32_t)(q * 16)), rb[li]);
         }
     }
     wave_sync();
