@@ -132,7 +132,7 @@ def work_model(w, prec: str) -> dict:
 
     Linear forms: the q-collapsed contraction, 2 * K * (entries computed), K =
     number of geometry-tensor terms per block (mass and Helmholtz compute the
-    upper triangle only; elasticity and Burgers every block), on the matrix
+    upper triangle only; elasticity the upper blocks, Burgers every block), on the matrix
     cores of the precision (degree-1 mass and Helmholtz in FP64/FP32 on the
     vector units). St Venant-Kirchhoff: svk_work."""
     d, p, form = w.mesh.d, w.degree, w.form
@@ -149,7 +149,10 @@ def work_model(w, prec: str) -> dict:
     elif form == "helmholtz":
         f = 2.0 * (nf + nd) * ns * (ns + 1) / 2
     elif form == "elasticity":
-        f = 2.0 * (max(nf, 1) * d * d) * (d * ns) ** 2
+        # the d(d+1)/2 upper blocks; the lower ones are their transposes
+        # (tet P3, on the panel engine, contracts all d^2 blocks)
+        nblk = d * d if (d == 3 and p == 3) else nd
+        f = 2.0 * (max(nf, 1) * d * d) * nblk * ns * ns
     else:
         f = 2.0 * (1 + nd + 2 * nf * d) * (d * ns) ** 2
     if p == 1 and form in ("mass", "helmholtz") and prec != "bf16x3":
