@@ -76,11 +76,14 @@ __host__ __device__ constexpr ElSizes el_sizes(int d, int p, int fd, int prec) {
     s.ring_bytes = s.ring * s.cellv * osz;
     s.wave_bytes = s.g_bytes + s.ring_bytes;
     s.tile_bytes = s.ks * 64 * fsz;  // fragments of one n-tile
-    s.rreg = s.nt * s.ks * (fsz / 4) <= 32;
     constexpr int L = 160 * 1024;
-    // two waves per SIMD when their rings fit, else one; then as many
-    // reference n-tiles in LDS as the rest of it holds
+    // two waves per SIMD when their rings fit, else one; the reference
+    // fragments in registers when few, or at one wave per SIMD (512 registers)
+    // when they take at most 160, else as many n-tiles in LDS as the rest of
+    // it holds
     s.waves = 8 * s.wave_bytes <= L ? 8 : 4;
+    const int rregs = s.nt * s.ks * (fsz / 4);
+    s.rreg = rregs <= 32 || (s.waves == 4 && rregs <= 160);
     const int spare = L - s.waves * s.wave_bytes;
     const int rl = spare > 0 ? spare / s.tile_bytes : 0;
     s.rlt = s.rreg ? 0 : (rl < s.nt ? rl : s.nt);
