@@ -141,13 +141,20 @@ __device__ __forceinline__ void el_put_G(const LinArgs& A, const ElWave<D, P, FD
     const int src = ci + 16 * g;
     int c, c2;
     el_block<D>(b, c, c2);
+    // K from the cell's lane; K K^T formed here (fewer permutes)
     double K[D][D], M[D][D];
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            K[a][k] = lane_get(cd.K[a][k], src);
-            M[a][k] = lane_get(cd.M[a][k], src);
+        for (int k = 0; k < D; ++k) K[a][k] = lane_get(cd.K[a][k], src);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) t += K[a][k] * K[e][k];
+            M[a][e] = t;
         }
     // every lane takes part in every permute (a permute reads nothing from a
     // lane that is switched off), then invalid rows are zeroed
@@ -173,7 +180,7 @@ __device__ __forceinline__ void el_put_G(const LinArgs& A, const ElWave<D, P, FD
             mu = ad * A.c0;
             lm = ad * A.c1;
         }
-        if (r < NF) {
+        if (NF % 4 == 0 || r < NF) {
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
