@@ -94,7 +94,7 @@ void add_all_prec(std::vector<LinEntry>& v) {
     v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_BF16X3>());
 }
 
-// the symmetric engine's other tile-shape variants (1, 2) for each precision
+// the symmetric engine's other tile-shape variants (1, 2, 3) for each precision
 template <int FORM, int D, int P, int FD>
 void add_variants(std::vector<LinEntry>& v) {
     static_assert(uses_scalar_engine(FORM), "tile-shape variants of the symmetric engine");
@@ -104,6 +104,9 @@ void add_variants(std::vector<LinEntry>& v) {
     v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F64, 2>());
     v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F32, 2>());
     v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_BF16X3, 2>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F64, 3>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_F32, 3>());
+    v.push_back(lin_entry<FORM, D, P, FD, dev::PREC_BF16X3, 3>());
 }
 
 void register_mass_tri(std::vector<LinEntry>& v);

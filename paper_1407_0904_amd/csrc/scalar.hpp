@@ -39,8 +39,12 @@ struct StageCfg {
 //   1  reference fragments staged in LDS once per workgroup, register budget
 //      of two waves per SIMD;
 //   2  reference fragments read through the L1/L2 caches at every use,
-//      register budget of two waves per SIMD.
-constexpr int kScalarVariants = 3;
+//      register budget of two waves per SIMD;
+//   3  as 2 at three waves per SIMD, with no gather prefetch across chunks
+//      (each chunk's gathers, contraction and stores in turn): launched with
+//      one workgroup per chunk, the many short-lived waves keep more stores
+//      in flight than a persistent grid does.
+constexpr int kScalarVariants = 4;
 
 template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 struct ScalarCfg {
@@ -208,7 +212,7 @@ __device__ inline void G_from_raw(const CellRaw<FORM, D, FD>& raw, const LinArgs
     }
 }
 
-constexpr int scalar_waves_per_eu(int var) { return var == 0 ? 1 : 2; }
+constexpr int scalar_waves_per_eu(int var) { return var == 0 ? 1 : (var == 3 ? 3 : 2); }
 
 template <int FORM, int D, int P, int FD, int PREC, int VAR = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(scalar_waves_per_eu(VAR))))
@@ -261,6 +265,37 @@ void k_scalar(LinArgs A) {
     auto cell_of = [&](int64_t ch) -> int64_t { return ch * 256 + wave * 64 + lane; };
 
     double Gv[KR];
+    if constexpr (VAR == 3) {
+        // no prefetch: gathers, G rows, contraction and stores of one chunk
+        // at a time (the last chunk bounds-checked)
+        for (; chunk < A.nchunks; chunk += GS) {
+            const int64_t wave_base = chunk * 256 + wave * 64;
+            if (wave_base >= A.ncells) break;  // wave-uniform
+            const int64_t last = A.ncells - 1;
+            const int64_t c = cell_of(chunk) < last ? cell_of(chunk) : last;
+            {
+                CellIdx<FORM, D, FD> ix;
+                CellRaw<FORM, D, FD> raw;
+                load_idx<FORM, D, FD>(A, c, ix);
+                load_raw<FORM, D, FD>(A, c, ix, raw);
+                G_from_raw<FORM, D, FD>(raw, A, cell_of(chunk) < A.ncells, Gv);
+            }
+            if (wave_base + 64 <= A.ncells) {
+                scalar_tile<FORM, D, P, FD, PREC, true, VAR>(A, W, Gv, 0, wave_base);
+                scalar_tile<FORM, D, P, FD, PREC, true, VAR>(A, W, Gv, 1, wave_base + 16);
+                scalar_tile<FORM, D, P, FD, PREC, true, VAR>(A, W, Gv, 2, wave_base + 32);
+                scalar_tile<FORM, D, P, FD, PREC, true, VAR>(A, W, Gv, 3, wave_base + 48);
+            } else {
+#pragma unroll 1
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t tile_base = wave_base + 16 * j;
+                    if (tile_base >= A.ncells) break;  // wave-uniform
+                    scalar_tile<FORM, D, P, FD, PREC, false, VAR>(A, W, Gv, j, tile_base);
+                }
+            }
+        }
+        return;
+    }
     CellIdx<FORM, D, FD> ix;  // indices of the chunk after next
     CellRaw<FORM, D, FD> raw;
     if (chunk < nfull) {

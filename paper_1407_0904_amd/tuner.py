@@ -8,8 +8,9 @@ call. Keys and candidates:
 
 * coffee_assemble (form, cell, degree, field degree, precision): the
   tile-shape variant of the symmetric engine (reference fragments in
-  registers at one wave per SIMD, in LDS at two waves per SIMD, or read
-  through the caches at two waves per SIMD; coffee_set_variant) x the grid
+  registers at one wave per SIMD, in LDS at two waves per SIMD, read through
+  the caches at two waves per SIMD, or through the caches at three waves per
+  SIMD with no prefetch across chunks; coffee_set_variant) x the grid
   multiplier (persistent grid of CUs x resident workgroups x m, or one
   workgroup per 256 cells);
 * mixed-batch bins (form, cell, degree, precision): store variant (LDS-staged
@@ -52,7 +53,7 @@ def _time(fn, reps: int = 7, warm: int = 2) -> float:
     return statistics.median(ts)
 
 
-def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4, 8, 64), variants=(0, 1, 2),
+def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4, 8, 64), variants=(0, 1, 2, 3),
                 log=print):
     """Best (tile-shape variant, grid multiplier) per precision for one named workload."""
     import torch

@@ -314,7 +314,7 @@ VARIANT_KEYS = [("helmholtz", 3, 2, 2), ("helmholtz", 3, 2, 1), ("mass", 3, 2, 2
                 ("helmholtz", 2, 3, 1), ("helmholtz", 2, 4, 1)]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("form,d,p,fd", VARIANT_KEYS)
 def test_tile_shape_variants(cf, oracle, form, d, p, fd, prec, variant):
