@@ -50,7 +50,8 @@ static coffee_status parse(const char* path) {
         if (!std::strcmp(kind, "linear")) {
             int form, cell, deg, fd, prec, gm, var = 0;
             const int nf = std::sscanf(line, "%*s %d %d %d %d %d %d %d", &form, &cell, &deg, &fd, &prec, &gm, &var);
-            if (nf < 6 || gm < 1 || var < 0 || var > 2) {
+            // tile-shape variants 0..3 of the symmetric engine
+            if (nf < 6 || gm < 1 || var < 0 || var > 3) {
                 st = COFFEE_E_INVALID_ARG;
                 break;
             }

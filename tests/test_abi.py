@@ -139,7 +139,7 @@ def test_tuning_cache_parsing(lib, tmp_path):
     bad = tmp_path / "bad.txt"
     bad.write_text("batch 0 2 1 1 1 100 0.25\n")
     assert f(str(bad).encode()) == 1
-    bad.write_text("linear 1 3 2 2 0 4 3\n")  # no tile-shape variant 3
+    bad.write_text("linear 1 3 2 2 0 4 4\n")  # no tile-shape variant 4
     assert f(str(bad).encode()) == 1
     bad.write_text("packed 0 2 1 1 96 0.25\n")
     assert f(str(bad).encode()) == 1
@@ -152,6 +152,10 @@ def test_tuning_cache_parsing(lib, tmp_path):
     assert f(str(out).encode()) == 0
     assert tuner.read_batch_costs(str(out)) == {("helmholtz", 3, 3, "fp32"): 1.5}
     assert tuner.read_batch_costs(str(out), "packed") == {("helmholtz", 3, 3, "fp32"): 1.25}
+    # the cache shipped with the package (the benchmark's launch configuration) loads
+    shipped = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1407_0904_amd",
+                           "tuning_mi355x.txt")
+    assert f(shipped.encode()) == 0
     assert f(None) == 0
 
 
