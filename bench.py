@@ -40,7 +40,7 @@ TUNING = os.path.join(ROOT, "paper_1407_0904_amd", "tuning_mi355x.txt")
 # HBM bytes per launch of the headline kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, scaled by a plain copy of known size (profiles/
 # k_scalar_helmholtz_p2_tet_fp64.md); valid only for the kernel they were taken on.
-TRAFFIC = {("helmholtz_p2_tet", "fp64"): 1401.3e6}
+TRAFFIC = {("helmholtz_p2_tet", "fp64"): 1374.4e6}
 
 WORKLOADS = {
     "helmholtz_p2_tet": "Helmholtz P2 tetrahedra, 64^3 x 6 cells, f P2 ~ U[0.5,1.5], jitter 10%, q = 4",
