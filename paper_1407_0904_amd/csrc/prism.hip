@@ -490,7 +490,10 @@ hipError_t launch_prism(const dev::PrismArgs& a, hipStream_t s, int dev_id) {
         hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
     if (attr != hipSuccess) return attr;
     const int64_t wgs_needed = (a.ntiles + C::WAVES - 1) / C::WAVES;
-    const int grid = grid_for(dev_id, kern, C::WAVES * 64, C::LDS_BYTES, wgs_needed, 1);
+    // grid multiplier from the tuning cache (prism keys: cell COFFEE_PRISM)
+    int tuned_variant = 0;
+    const int tuned = tuned_linear(FORM, COFFEE_PRISM, P, FD, PREC, &tuned_variant);
+    const int grid = grid_for(dev_id, kern, C::WAVES * 64, C::LDS_BYTES, wgs_needed, tuned > 0 ? tuned : 1);
     hipLaunchKernelGGL((dev::k_prism<FORM, P, FD, PREC, NQ>), dim3(grid), dim3(C::WAVES * 64), C::LDS_BYTES, s, a);
     return hipGetLastError();
 }

@@ -31,7 +31,7 @@ import sys
 
 import numpy as np
 
-FORM_IDS = {"mass": 0, "helmholtz": 1, "elasticity": 2, "burgers": 3}
+FORM_IDS = {"mass": 0, "helmholtz": 1, "elasticity": 2, "burgers": 3, "diffusion": 7}
 PREC_IDS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
@@ -66,16 +66,16 @@ def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4
     fd = w.fields[0].degree if w.fields else 0
     entries = []
     for prec in precisions:
-        out = torch.empty(coffee.output_shape(w.form, w.mesh.ncells, w.mesh.d, w.degree),
+        out = torch.empty(coffee.output_shape(w.form, w.mesh.ncells, w.mesh.cell, w.degree),
                           dtype=torch.float64 if prec == "fp64" else torch.float32, device=dev)
         best = None
         for var in variants:
-            if var and not coffee.coffee_has_variant(w.form, w.mesh.d, w.degree, fd, prec, var):
+            if var and not coffee.coffee_has_variant(w.form, w.mesh.cell, w.degree, fd, prec, var):
                 continue
             coffee.coffee_set_variant(var)
             for m in candidates:
                 coffee.coffee_set_launch_options(m)
-                call = coffee.PreparedAssemble(w.form, w.mesh.d, w.degree, coords, c2v, coeffs=fields,
+                call = coffee.PreparedAssemble(w.form, w.mesh.cell, w.degree, coords, c2v, coeffs=fields,
                                                constants=w.constants, quad_degree=w.quad_degree, precision=prec,
                                                out=out)
                 ms = _time(call)
@@ -84,7 +84,7 @@ def tune_linear(workload_name: str, precisions=("fp64",), candidates=(1, 2, 3, 4
                     best = (var, m, ms)
         coffee.coffee_set_launch_options(0)
         coffee.coffee_set_variant(-1)
-        entries.append(("linear", FORM_IDS[w.form], w.mesh.d, w.degree, fd, PREC_IDS[prec], best[1], best[0]))
+        entries.append(("linear", FORM_IDS[w.form], w.mesh.cell, w.degree, fd, PREC_IDS[prec], best[1], best[0]))
         del out
     return entries
 
@@ -210,6 +210,9 @@ def main(argv=None):
         entries += tune_linear("helmholtz_p1_tri", ("fp64",))
         entries += tune_linear("elasticity_p2_tet", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 4, 8))
         entries += tune_linear("burgers_p2_tet", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 4, 8))
+        entries += tune_linear("helmholtz_p1_prism", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 4), variants=(0,))
+        entries += tune_linear("diffusion_p2_prism", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 3, 4, 8),
+                               variants=(0,))
         mb = inputs.mixed_batch()
     else:
         mb = inputs.mixed_batch(n_tri=64, n_tet=12, tri_counts=(3000, 2000, 1500, 1000),

@@ -133,10 +133,28 @@ def test_vector_ragged_counts(cf, oracle, form, p, prec):
         assert err < TOL[prec]
 
 
-def test_full_size_elasticity_p2_tet_sampled(cf, oracle):
+TUNING = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1407_0904_amd",
+                      "tuning_mi355x.txt")
+
+
+@pytest.fixture(params=["default", "tuned"])
+def launch_config(request, cf):
+    """The library's default launch shape, and the shipped tuning cache that
+    the benchmark loads before it times anything (grid multipliers per kernel
+    instance); the defaults are restored afterwards."""
+    if request.param == "tuned":
+        assert os.path.exists(TUNING), TUNING
+        cf.coffee_load_tuning(TUNING)
+    yield request.param
+    cf.coffee_load_tuning(None)
+    cf.coffee_set_launch_options(0)
+
+
+def test_full_size_elasticity_p2_tet_sampled(cf, oracle, launch_config):
     """The 663,552-cell elasticity P2 tetrahedron workload (P1 Lame fields) in
-    the benchmark's launch configuration: sampled cells against the oracle in
-    every precision, and rigid translations in the kernel of all cells."""
+    the library's default launch shape and in the tuned one the benchmark
+    times: sampled cells against the oracle in every precision, and rigid
+    translations in the kernel of all cells."""
     import torch
     from gpu_util import TOL, cell_rel_err, to_dev
     w = I.workload("elasticity_p2_tet")
@@ -206,23 +224,6 @@ def test_p1_ragged_counts(cf, oracle, form, d, fd, prec):
         got = assemble_gpu(form, sub, 1, flds, precision=prec).cpu().numpy()
         err = cell_rel_err(got, ref)
         assert err < TOL[prec], (n, err)
-
-
-TUNING = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1407_0904_amd",
-                      "tuning_mi355x.txt")
-
-
-@pytest.fixture(params=["default", "tuned"])
-def launch_config(request, cf):
-    """The library's default launch shape, and the shipped tuning cache that
-    the benchmark loads before it times anything (grid multipliers per kernel
-    instance); the defaults are restored afterwards."""
-    if request.param == "tuned":
-        assert os.path.exists(TUNING), TUNING
-        cf.coffee_load_tuning(TUNING)
-    yield request.param
-    cf.coffee_load_tuning(None)
-    cf.coffee_set_launch_options(0)
 
 
 def test_full_size_helmholtz_p2_tet_sampled(cf, oracle, launch_config):
