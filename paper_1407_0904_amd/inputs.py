@@ -23,7 +23,10 @@ available; these stand in for them):
   each base triangle (cell t n + k). Jitter moves interior vertices in all
   three directions, so the prisms are not affine images of the reference
   prism (their top and bottom triangles differ and their sides are warped).
-* Vertex index v = i + (n+1) j (+ (n+1)^2 k).
+* Vertex index v = i + (n+1) j (+ (n+1)^2 k) on triangles and tetrahedra; on
+  prisms the vertices are numbered column by column as extruded meshes are,
+  v = b (n+1) + k for base vertex b = i + (n+1) j and level k (the jitter is
+  drawn in lattice order, then the vertices are renumbered).
 * Jitter: every coordinate of every interior vertex moves by an independent
   draw from U[-r h, r h] (h = 1/n); boundary vertices do not move, so the
   domain measure stays exactly 1.
@@ -167,18 +170,27 @@ def make_mesh(d: int, n: int, jitter_frac: float, rng: np.random.Generator) -> M
 
 
 def prism_cells(n: int) -> np.ndarray:
-    """Connectivity [2 n^2 n, 6] int32 of the extruded split unit square."""
+    """Connectivity [2 n^2 n, 6] int32 of the extruded split unit square,
+    numbered column by column as extruded meshes are: cell (t, k) = t n + k
+    for base triangle t and layer k, vertex (b, k) = b (n+1) + k for base
+    vertex b and level k."""
     m = n + 1
-    base = square_cells(n).astype(np.int64)              # [T, 3] on the k = 0 layer
+    base = square_cells(n).astype(np.int64)              # [T, 3] base-lattice vertices
     k = np.arange(n, dtype=np.int64)
-    bot = base[:, None, :] + (m * m) * k[None, :, None]  # [T, n, 3]
-    top = bot + m * m
+    bot = base[:, None, :] * m + k[None, :, None]        # [T, n, 3]
+    top = bot + 1
     cells = np.stack([bot[..., 0], top[..., 0], bot[..., 1], top[..., 1], bot[..., 2], top[..., 2]], axis=-1)
     return cells.reshape(-1, 6).astype(np.int32)
 
 
 def make_prism_mesh(n: int, jitter_frac: float, rng: np.random.Generator) -> Mesh:
-    coords = jitter(lattice_coords(n, 3), n, jitter_frac, rng)
+    # jitter drawn in lattice order (i + m j + m^2 k), then the vertices are
+    # renumbered column by column: new index b m + k holds lattice point b + m^2 k
+    m = n + 1
+    lat = jitter(lattice_coords(n, 3), n, jitter_frac, rng)
+    b = np.arange(m * m, dtype=np.int64)
+    k = np.arange(m, dtype=np.int64)
+    coords = lat[(b[:, None] + (m * m) * k[None, :]).reshape(-1)]
     return Mesh(d=3, n=n, coords=np.ascontiguousarray(coords), cells=np.ascontiguousarray(prism_cells(n)))
 
 
