@@ -69,7 +69,7 @@ def test_scalar_forms(cf, oracle, form, d, p, fd, prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("d,p,fields", [(3, 2, True), (3, 1, True), (3, 2, False), (2, 2, True), (3, 3, True),
-                                        (2, 3, False)])
+                                        (2, 3, False), (2, 1, True), (2, 1, False), (3, 1, False), (2, 3, True)])
 def test_elasticity(cf, oracle, d, p, fields, prec):
     from gpu_util import TOL, assemble_gpu, cell_rel_err
     rng = np.random.default_rng(7 + p)
