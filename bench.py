@@ -51,6 +51,7 @@ WORKLOADS = {
     "svk_p2_tet": "St Venant-Kirchhoff Jacobian vector P2 tetrahedra, 32^3 x 6 cells, u P2 ~ N(0, 0.01^2), q = 4",
     "helmholtz_p1_prism": "Helmholtz P1 warped prisms, 64^2 x 2 x 64 cells, f P1 ~ U[0.5,1.5], jitter 10%, q = 2",
     "diffusion_p2_prism": "diffusion P2 warped prisms, 64^2 x 2 x 64 cells, kappa = dt = 1, jitter 10%, q = 4",
+    "diffusion_p3_prism": "diffusion P3 warped prisms, 32^2 x 2 x 32 cells, kappa = dt = 1, jitter 10%, q = 6",
 }
 
 log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
@@ -455,7 +456,7 @@ def forms_section(ctx):
                 res.append(measure_forward(ctx, w, prec, sample_n=150))
         w.form = "svk_energy"
         res.append(measure_adjoint(ctx, w, name))
-    for name in ("burgers_p1_tet", "burgers_p2_tet", "helmholtz_p1_prism", "diffusion_p2_prism"):
+    for name in ("burgers_p1_tet", "burgers_p2_tet", "helmholtz_p1_prism", "diffusion_p2_prism", "diffusion_p3_prism"):
         w = I.workload(name)
         for prec in ("fp64", "fp32", "bf16x3"):
             res.append(measure_forward(ctx, w, prec, sample_n=150))

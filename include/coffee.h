@@ -147,8 +147,8 @@ int coffee_tensor_dim(int form, int cell, int degree);
  * Prisms: cell_to_vertex is [ncells][6] (vertex order above) and coords
  * [nvert][3]; COFFEE_MASS and COFFEE_HELMHOLTZ (no field, or one degree-1
  * prism field: 6 dofs per cell through cell_to_dof or cell-major) and
- * COFFEE_DIFFUSION, at degree 1 (6 x 6) and 2 (18 x 18), with the default
- * rule (q = 2p, 8 and 27 points), in every precision.
+ * COFFEE_DIFFUSION, at degree 1 (6 x 6), 2 (18 x 18) and 3 (40 x 40), with the
+ * default rule (q = 2p: 8, 27 and 64 points), in every precision.
  * Errors: COFFEE_E_INVALID_ARG (null pointers, bad enums, negative sizes,
  * misaligned out,
  * field shape/count not matching the form), COFFEE_E_UNSUPPORTED (degree or

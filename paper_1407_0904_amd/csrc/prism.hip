@@ -402,6 +402,177 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 
+
+// ---------------------------------------------------------------- degree >= 3
+// At degree 3 (40 dofs, 820 unique entries in 52 n-tiles, 64 points, K = 448
+// for Helmholtz) one wave cannot hold the accumulators of all n-tiles, and 16
+// cells' matrices (205 KB in FP64) are larger than the LDS. A cell's matrix
+// written a few entries at a time over a long contraction leaves partial lines
+// that the L2 evicts before they are complete, so the matrices go out through
+// a staging area, a few whole cells at a time.
+//
+// The four waves of a workgroup share one 16-cell tile: all 256 threads form
+// the tile's G rows in LDS once (16 threads per cell, each a sixteenth of the
+// points), each wave contracts them with its quarter of the n-tiles (the R
+// fragments of step s + 1 load from L2 during the products of step s), and
+// then, in four passes of four cells, the waves write their accumulators
+// (both mirrored entries) into the staging area, which reuses the G rows'
+// LDS, and the workgroup copies those cells out as contiguous 16-byte stores.
+template <int FORM, int P, int FD, int PREC, int NQ>
+struct PrismBigCfg {
+    using C = PrismCfg<FORM, P, FD, PREC, NQ>;
+    static constexpr int WAVES = 4;
+    static constexpr int TCH = (C::NT + WAVES - 1) / WAVES;  // n-tiles per wave
+    static constexpr int GT_BYTES = 16 * C::ROW * (int)sizeof(typename C::g_t);
+    static constexpr int ST_BYTES = 4 * C::NN * (int)sizeof(typename C::out_t);  // four cells
+    static constexpr int LDS_BYTES = ((GT_BYTES > ST_BYTES ? GT_BYTES : ST_BYTES) + 15) / 16 * 16;
+    static_assert(LDS_BYTES <= 160 * 1024, "G rows and staging fit the LDS");
+    static_assert(C::NN * (int)sizeof(typename C::out_t) % 16 == 0, "cell matrices of whole 16-byte vectors");
+};
+
+template <int FORM, int P, int FD, int PREC, int NQ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_prism_big(PrismArgs A) {
+    using C = PrismCfg<FORM, P, FD, PREC, NQ>;
+    using B = PrismBigCfg<FORM, P, FD, PREC, NQ>;
+    using g_t = typename C::g_t;
+    using frag_t = typename C::frag_t;
+    using acc_t = typename C::acc_t;
+    using out_t = typename C::out_t;
+    constexpr int NS = C::NS, NN = C::NN, NU = C::NU, NT = C::NT, KS = C::KS, JQ = C::JQ, KR = C::KR,
+                  ROW = C::ROW, TCH = B::TCH;
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    __shared__ double sq[NQ * 4];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    g_t* gt = reinterpret_cast<g_t*>(lds);
+    out_t* st = reinterpret_cast<out_t*>(lds);
+    const frag_t* rf = reinterpret_cast<const frag_t*>(A.rfrag);
+    out_t* out = reinterpret_cast<out_t*>(A.out);
+    const int t0 = wave * TCH;  // this wave's n-tiles t0 .. t0 + TCH - 1
+
+    // staging offsets of this lane's unique entries u = 16 t + (lane & 15):
+    // (a, b), a <= b, row-major over the upper triangle (low half), and its
+    // mirror (b, a) (high half)
+    static_assert(NN <= 65536, "offsets in 16 bits");
+    unsigned off[TCH];
+#pragma unroll
+    for (int i = 0; i < TCH; ++i) {
+        int u = 16 * (t0 + i) + (lane & 15), a = 0;
+        while (a < NS - 1 && u >= NS - a) {
+            u -= NS - a;
+            ++a;
+        }
+        off[i] = (unsigned)(a * NS + a + u) | (unsigned)((a + u) * NS + a) << 16;
+    }
+    for (int i = tid; i < NQ * 4; i += blockDim.x) sq[i] = gload(A.qtab + i);
+    // the R fragments of this wave's n-tiles at k-step g (tiles past NT repeat
+    // the last one; their products are never stored)
+    auto load_b = [&](frag_t* b, int g) {
+#pragma unroll
+        for (int i = 0; i < TCH; ++i) b[i] = gload(rf + ((t0 + i < NT ? t0 + i : NT - 1) * KS + g) * 64 + lane);
+    };
+
+    for (int64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+        const int64_t base = tile * 16;
+        __syncthreads();  // the previous tile's staging reads are done (and sq is loaded)
+
+        // G rows: thread (cell col, point group pg) forms points pg, pg + 16, ...
+        {
+            const int col = tid & 15, pg = tid >> 4;
+            const bool valid = base + col < A.ncells;
+            const int64_t cell = valid ? base + col : A.ncells - 1;
+            PrismIdx ix;
+            PrismRaw<FD> raw;
+            prism_idx<FD>(A, cell, ix);
+            prism_raw<FD>(A, cell, ix, raw);
+            double e[7][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                e[0][i] = raw.x[2][i] - raw.x[0][i];
+                e[1][i] = raw.x[3][i] - raw.x[1][i];
+                e[2][i] = raw.x[4][i] - raw.x[0][i];
+                e[3][i] = raw.x[5][i] - raw.x[1][i];
+                e[4][i] = raw.x[1][i] - raw.x[0][i];
+                e[5][i] = raw.x[3][i] - raw.x[2][i];
+                e[6][i] = raw.x[5][i] - raw.x[4][i];
+            }
+            g_t* row = gt + col * ROW;
+            // k padding past the G entries (the staging area overwrote it)
+            constexpr int KFILL = PREC == PREC_BF16X3 ? 3 * KR : KR;
+            for (int k = KFILL + pg; k < KS * kstep(PREC); k += 16) row[k] = g_t(0);
+#pragma unroll 1
+            for (int q = pg; q < NQ; q += 16) {
+                const double X = sq[4 * q], Y = sq[4 * q + 1], Z = sq[4 * q + 2], W = sq[4 * q + 3];
+                const double zb = 1.0 - Z, l0 = 1.0 - X - Y;
+                double J[3][3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    J[i][0] = zb * e[0][i] + Z * e[1][i];
+                    J[i][1] = zb * e[2][i] + Z * e[3][i];
+                    J[i][2] = l0 * e[4][i] + X * e[5][i] + Y * e[6][i];
+                }
+                double K[3][3], adet;
+                prism_inverse(J, K, adet);
+                const double w = valid ? W * adet : 0.0;
+                int j = q * JQ;
+                if constexpr (FORM != F_MASS) {
+                    const double sc = FORM == F_DIFF ? w * A.kdt : w;
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+#pragma unroll
+                        for (int be = al; be < 3; ++be) {
+                            const double sv = K[al][0] * K[be][0] + K[al][1] * K[be][1] + K[al][2] * K[be][2];
+                            put_g<PREC, KR>(row, j++, sc * sv);
+                        }
+                }
+                if constexpr (FORM != F_DIFF) {
+                    double fq = 1.0;
+                    if constexpr (FD > 0)
+                        fq = (l0 * raw.f[0] + X * raw.f[2] + Y * raw.f[4]) * zb +
+                             (l0 * raw.f[1] + X * raw.f[3] + Y * raw.f[5]) * Z;
+                    put_g<PREC, KR>(row, j, w * fq);
+                }
+            }
+        }
+        frag_t b[TCH];
+        load_b(b, 0);
+        __syncthreads();
+
+        // contraction of the 16 cells' G rows with this wave's n-tiles
+        acc_t acc[TCH];
+#pragma unroll
+        for (int i = 0; i < TCH; ++i) acc[i] = acc_t{0, 0, 0, 0};
+#pragma unroll 1
+        for (int s = 0; s < KS; ++s) {
+            const frag_t a0 = load_afrag<PREC>(gt, ROW, lane, s);
+#pragma unroll
+            for (int i = 0; i < TCH; ++i) acc[i] = mfma<PREC>(a0, b[i], acc[i]);
+            if (s + 1 < KS) load_b(b, s + 1);  // in flight during these products
+        }
+
+        // four passes: the cells of accumulator element v (slot = lane / 16)
+        constexpr int NV1 = NN * (int)sizeof(out_t) / 16;  // 16-byte vectors per cell
+        const u32x4p* s4 = reinterpret_cast<const u32x4p*>(st);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            __syncthreads();  // G reads (first pass) or the previous pass's copies are done
+#pragma unroll
+            for (int i = 0; i < TCH; ++i) {
+                if (16 * (t0 + i) + (lane & 15) >= NU) continue;
+                const out_t x = (out_t)acc[i][v];
+                st[(lane >> 4) * NN + (off[i] & 0xffff)] = x;
+                st[(lane >> 4) * NN + (off[i] >> 16)] = x;
+            }
+            __syncthreads();
+            for (int k = tid; k < 4 * NV1; k += blockDim.x) {
+                const int slot = k / NV1;
+                const int64_t c = base + acc_row<PREC>(16 * slot, v);
+                if (c < A.ncells)
+                    gstore_nt(reinterpret_cast<u32x4p*>(out + c * NN) + (k - slot * NV1), s4[k]);
+            }
+        }
+    }
+}
+
 }  // namespace dev
 
 namespace {
@@ -498,11 +669,33 @@ hipError_t launch_prism(const dev::PrismArgs& a, hipStream_t s, int dev_id) {
     return hipGetLastError();
 }
 
+template <int FORM, int P, int FD, int PREC, int NQ>
+hipError_t launch_prism_big(const dev::PrismArgs& a, hipStream_t s, int dev_id) {
+    using B = dev::PrismBigCfg<FORM, P, FD, PREC, NQ>;
+    const void* kern = reinterpret_cast<const void*>(&dev::k_prism_big<FORM, P, FD, PREC, NQ>);
+    static const hipError_t attr =
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, B::LDS_BYTES);
+    if (attr != hipSuccess) return attr;
+    const int64_t wgs_needed = a.ntiles;  // one 16-cell tile per workgroup at a time
+    int tuned_variant = 0;
+    const int tuned = tuned_linear(FORM, COFFEE_PRISM, P, FD, PREC, &tuned_variant);
+    const int grid = grid_for(dev_id, kern, B::WAVES * 64, B::LDS_BYTES, wgs_needed, tuned > 0 ? tuned : 1);
+    hipLaunchKernelGGL((dev::k_prism_big<FORM, P, FD, PREC, NQ>), dim3(grid), dim3(B::WAVES * 64), B::LDS_BYTES, s,
+                       a);
+    return hipGetLastError();
+}
+
 template <int FORM, int P, int FD, int NQ>
 hipError_t launch_prism_prec(int prec, const dev::PrismArgs& a, hipStream_t s, int dev_id) {
-    if (prec == COFFEE_FP64) return launch_prism<FORM, P, FD, dev::PREC_F64, NQ>(a, s, dev_id);
-    if (prec == COFFEE_FP32) return launch_prism<FORM, P, FD, dev::PREC_F32, NQ>(a, s, dev_id);
-    return launch_prism<FORM, P, FD, dev::PREC_BF16X3, NQ>(a, s, dev_id);
+    if constexpr (P >= 3) {
+        if (prec == COFFEE_FP64) return launch_prism_big<FORM, P, FD, dev::PREC_F64, NQ>(a, s, dev_id);
+        if (prec == COFFEE_FP32) return launch_prism_big<FORM, P, FD, dev::PREC_F32, NQ>(a, s, dev_id);
+        return launch_prism_big<FORM, P, FD, dev::PREC_BF16X3, NQ>(a, s, dev_id);
+    } else {
+        if (prec == COFFEE_FP64) return launch_prism<FORM, P, FD, dev::PREC_F64, NQ>(a, s, dev_id);
+        if (prec == COFFEE_FP32) return launch_prism<FORM, P, FD, dev::PREC_F32, NQ>(a, s, dev_id);
+        return launch_prism<FORM, P, FD, dev::PREC_BF16X3, NQ>(a, s, dev_id);
+    }
 }
 
 template <int P, int NQ>
@@ -523,8 +716,8 @@ hipError_t launch_prism_form(int form, int fd, int prec, const dev::PrismArgs& a
 coffee_status assemble_prism(int form, int degree, int quad, int precision, const double* coords,
                              const int32_t* c2v, int64_t ncells, const coffee_field* coeffs, int ncoeff,
                              const double* constants, int nconst, void* out, void* hip_stream) {
-    // compiled: the default rule (q = 2p) at degree 1 (8 points) and 2 (27 points)
-    if (degree < 1 || degree > 2 || quad != 2 * degree) return COFFEE_E_UNSUPPORTED;
+    // compiled: the default rule (q = 2p) at degree 1 (8 points), 2 (27 points) and 3 (64 points)
+    if (degree < 1 || degree > 3 || quad != 2 * degree) return COFFEE_E_UNSUPPORTED;
     if (ncells == 0) return COFFEE_OK;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return COFFEE_E_HIP;
@@ -544,8 +737,9 @@ coffee_status assemble_prism(int form, int degree, int quad, int precision, cons
     a.ntiles = (ncells + 15) / 16;
     const int fd = ncoeff >= 1 ? 1 : 0;
     hipStream_t s = (hipStream_t)hip_stream;
-    const hipError_t e = degree == 1 ? launch_prism_form<1, 8>(form, fd, precision, a, s, dev)
-                                     : launch_prism_form<2, 27>(form, fd, precision, a, s, dev);
+    const hipError_t e = degree == 1   ? launch_prism_form<1, 8>(form, fd, precision, a, s, dev)
+                         : degree == 2 ? launch_prism_form<2, 27>(form, fd, precision, a, s, dev)
+                                       : launch_prism_form<3, 64>(form, fd, precision, a, s, dev);
     return e == hipSuccess ? COFFEE_OK : COFFEE_E_HIP;
 }
 

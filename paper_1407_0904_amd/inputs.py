@@ -259,12 +259,14 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> Worklo
     burgers_p1_tet / burgers_p2_tet  Burgers Jacobian, w ~ U[-1,1], nu = 1/dt = 1, q = 2p+1 (n=48)
     helmholtz_p1_prism  Helmholtz P1 on warped prisms, f P1 ~ U[0.5,1.5], jitter 10%, q=2 (n=64: 524,288 cells)
     diffusion_p2_prism  diffusion P2 on warped prisms, kappa = 1, dt = 1, jitter 10%, q=4 (n=64)
+    diffusion_p3_prism  diffusion P3 on warped prisms, kappa = 1, dt = 1, jitter 10%, q=6 (n=32: 65,536 cells)
     mass_pK_tri / helmholtz_pK_tet etc. are built by mixed_batch().
     """
     defaults = {
         "helmholtz_p1_tri": 64, "helmholtz_p2_tet": 64, "elasticity_p2_tet": 48,
         "elasticity_p1_tet": 48, "svk_p1_tet": 32, "svk_p2_tet": 32,
         "burgers_p1_tet": 48, "burgers_p2_tet": 48, "helmholtz_p1_prism": 64, "diffusion_p2_prism": 64,
+        "diffusion_p3_prism": 32,
     }
     if name not in defaults:
         raise KeyError(name)
@@ -301,9 +303,10 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> Worklo
         mesh = make_prism_mesh(n, 0.10, rng)
         f = _p1_field(mesh, rng.uniform(0.5, 1.5, size=mesh.nvert), 1)
         return Workload(name, "helmholtz", mesh, 1, 2, [f])
-    if name == "diffusion_p2_prism":
+    if name in ("diffusion_p2_prism", "diffusion_p3_prism"):
+        p = 2 if name == "diffusion_p2_prism" else 3
         mesh = make_prism_mesh(n, 0.10, rng)
-        return Workload(name, "diffusion", mesh, 2, 4, [], [1.0, 1.0])
+        return Workload(name, "diffusion", mesh, p, 2 * p, [], [1.0, 1.0])
     if name in ("burgers_p1_tet", "burgers_p2_tet"):
         p = 1 if name == "burgers_p1_tet" else 2
         mesh = make_mesh(3, n, 0.10, rng)

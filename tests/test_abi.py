@@ -65,10 +65,10 @@ def test_validation_before_any_hip_call(lib):
     assert _assemble(lib, form=2, coords=dummy, c2v=dummy, out=dummy) == 1
     # Burgers needs one vector field
     assert _assemble(lib, form=3, coords=dummy, c2v=dummy, out=dummy) == 1
-    # prisms (cell 6): vector forms, degree 3 and a non-default rule are outside the compiled set;
+    # prisms (cell 6): vector forms, degree 4 and a non-default rule are outside the compiled set;
     # diffusion (form 7) takes no field
     assert _assemble(lib, form=2, cell=6, coords=dummy, c2v=dummy, out=dummy) == 2
-    assert _assemble(lib, form=1, cell=6, degree=3, coords=dummy, c2v=dummy, out=dummy) == 2
+    assert _assemble(lib, form=1, cell=6, degree=4, coords=dummy, c2v=dummy, out=dummy) == 2
     assert _assemble(lib, form=7, cell=6, q=3, coords=dummy, c2v=dummy, out=dummy) == 2
     assert _assemble(lib, form=8, coords=dummy, c2v=dummy, out=dummy) == 1
 

@@ -56,7 +56,7 @@ PRISM_CASES = [("mass", "none"), ("mass", "mapped"), ("helmholtz", "none"), ("he
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, 3])
 @pytest.mark.parametrize("form,kind", PRISM_CASES)
 def test_prism_vs_oracle(cf, oracle, form, kind, p, prec):
     from gpu_util import TOL, assemble_gpu, cell_rel_err
@@ -79,14 +79,14 @@ def test_prism_ragged_counts(cf, oracle, ncells):
     rng = np.random.default_rng(ncells)
     full = I.make_prism_mesh(5, 0.15, rng)
     mesh = I.Mesh(d=3, n=5, coords=full.coords, cells=np.ascontiguousarray(full.cells[:ncells]))
-    for p in (1, 2):
+    for p in (1, 2, 3):
         ref = oracle.assemble("helmholtz", mesh, p)
         got = assemble_gpu("helmholtz", mesh, p, []).cpu().numpy()
         assert got.shape == ref.shape
         assert cell_rel_err(got, ref) < 1e-12
 
 
-@pytest.mark.parametrize("name,p,form", [("p1", 1, "helmholtz"), ("p2", 2, "diffusion")])
+@pytest.mark.parametrize("name,p,form", [("p1", 1, "helmholtz"), ("p2", 2, "diffusion"), ("p3", 3, "diffusion")])
 def test_prism_full_size_sampled(cf, oracle, name, p, form):
     """The benchmark's prism workloads at full size, in its launch
     configuration (the shipped tuning cache): 2,000 sampled cells against the
@@ -127,7 +127,7 @@ def _prism_full_size(cf, oracle, name, p, form):
 
 
 def test_prism_errors_and_geometry_check(cf):
-    """Refusals are reported (prism adjoint, non-default rule, degree 3,
+    """Refusals are reported (prism adjoint, non-default rule, degree 4,
     vector forms), an empty mesh is accepted, and the geometry check finds an
     inverted prism."""
     import torch
@@ -140,7 +140,7 @@ def test_prism_errors_and_geometry_check(cf):
             cf.coffee_assemble("helmholtz", PRISM, 1, coords, c2v, **kwargs)
         assert e.value.code == U
     with pytest.raises(cf.CoffeeError) as e:
-        cf.coffee_assemble("helmholtz", PRISM, 3, coords, c2v)
+        cf.coffee_assemble("helmholtz", PRISM, 4, coords, c2v)
     assert e.value.code == U
     with pytest.raises(cf.CoffeeError) as e:
         cf.coffee_assemble("svk_energy", PRISM, 1, coords, c2v,
