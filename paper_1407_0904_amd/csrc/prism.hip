@@ -418,6 +418,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // then, in four passes of four cells, the waves write their accumulators
 // (both mirrored entries) into the staging area, which reuses the G rows'
 // LDS, and the workgroup copies those cells out as contiguous 16-byte stores.
+// Word 3 of a raw buffer resource on gfx9-family chips: 32-bit data format
+// (a zero format would make untyped buffer accesses read zeros).
+constexpr int kBufferWord3 = 0x00020000;
+
+// One MFMA fragment (8, 4 or 16 bytes) from a raw buffer.
+template <typename F>
+__device__ inline F buffer_frag(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(F) == 4) {
+        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else if constexpr (sizeof(F) == 8) {
+        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else {
+        static_assert(sizeof(F) == 16, "fragment of 4, 8 or 16 bytes");
+        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    }
+}
+
 template <int FORM, int P, int FD, int PREC, int NQ>
 struct PrismBigCfg {
     using C = PrismCfg<FORM, P, FD, PREC, NQ>;
@@ -447,7 +464,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     out_t* st = reinterpret_cast<out_t*>(lds);
     const frag_t* rf = reinterpret_cast<const frag_t*>(A.rfrag);
     out_t* out = reinterpret_cast<out_t*>(A.out);
-    const int t0 = wave * TCH;  // this wave's n-tiles t0 .. t0 + TCH - 1
+    const int t0 = __builtin_amdgcn_readfirstlane(wave) * TCH;  // this wave's n-tiles t0 .. t0 + TCH - 1 (scalar)
 
     // staging offsets of this lane's unique entries u = 16 t + (lane & 15):
     // (a, b), a <= b, row-major over the upper triangle (low half), and its
@@ -464,11 +481,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         off[i] = (unsigned)(a * NS + a + u) | (unsigned)((a + u) * NS + a) << 16;
     }
     for (int i = tid; i < NQ * 4; i += blockDim.x) sq[i] = gload(A.qtab + i);
-    // the R fragments of this wave's n-tiles at k-step g (tiles past NT repeat
-    // the last one; their products are never stored)
+    // the R fragments of this wave's n-tiles at k-step g, as buffer loads: the
+    // lane's offset in one register, each tile's offset a scalar (tiles past
+    // NT repeat the last one; their products are never stored)
+    constexpr unsigned FB = sizeof(frag_t);
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<frag_t*>(rf), (short)0, NT * KS * 64 * (int)FB, kBufferWord3);
     auto load_b = [&](frag_t* b, int g) {
+        const unsigned vo = ((unsigned)(t0 * KS + g) * 64 + lane) * FB;
 #pragma unroll
-        for (int i = 0; i < TCH; ++i) b[i] = gload(rf + ((t0 + i < NT ? t0 + i : NT - 1) * KS + g) * 64 + lane);
+        for (int i = 0; i < TCH; ++i)
+            b[i] = buffer_frag<frag_t>(rsrc, vo, (unsigned)((t0 + i < NT ? i : NT - 1 - t0) * KS * 64) * FB);
     };
 
     for (int64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
