@@ -73,6 +73,23 @@ struct PrismCfg {
     static constexpr bool RREG = REGB <= 64;  // reference fragments held in registers
 };
 
+// Word 3 of a raw buffer resource on gfx9-family chips: 32-bit data format
+// (a zero format would make untyped buffer accesses read zeros).
+constexpr int kBufferWord3 = 0x00020000;
+
+// One MFMA fragment (8, 4 or 16 bytes) from a raw buffer.
+template <typename F>
+__device__ inline F buffer_frag(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(F) == 4) {
+        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    } else if constexpr (sizeof(F) == 8) {
+        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else {
+        static_assert(sizeof(F) == 16, "fragment of 4, 8 or 16 bytes");
+        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    }
+}
+
 struct PrismArgs {
     const double* coords;  // [nvert][3]
     const int32_t* c2v;    // [ncells][6]
@@ -183,6 +200,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         ua[t] = a;
         ub[t] = a + u;
     }
+    constexpr unsigned FB = sizeof(frag_t);
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<frag_t*>(rf), (short)0, NT * KS * 64 * (int)FB, kBufferWord3);
+    const unsigned vlane = lane * FB;
     frag_t rreg[C::RREG ? NT : 1][C::RREG ? KS : 1];
     if constexpr (C::RREG) {
 #pragma unroll
@@ -322,21 +343,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
                 for (int t = 0; t < NT; ++t) acc[t] = mfma<PREC>(afr[s], rreg[t][s], acc[t]);
         } else {
-            // fragments through the caches, the next k-step's loads issued
-            // before this k-step's products
-            frag_t bc[NT], bn[NT];
+            // fragments through the caches as buffer loads (the lane's offset
+            // in one register, each n-tile's a constant), the next k-step's
+            // loads in flight during this k-step's products
+            frag_t b[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) bc[t] = gload(rf + t * KS * 64 + lane);
+            for (int t = 0; t < NT; ++t) b[t] = buffer_frag<frag_t>(rsrc, vlane, t * KS * 64 * FB);
 #pragma unroll 1
             for (int s = 0; s < KS; ++s) {
-                const int sn = s + 1 < KS ? s + 1 : s;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) bn[t] = gload(rf + (t * KS + sn) * 64 + lane);
                 const frag_t a = load_afrag<PREC>(gt, ROW, lane, s);
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] = mfma<PREC>(a, bc[t], acc[t]);
+                for (int t = 0; t < NT; ++t) acc[t] = mfma<PREC>(a, b[t], acc[t]);
+                if (s + 1 < KS) {
 #pragma unroll
-                for (int t = 0; t < NT; ++t) bc[t] = bn[t];
+                    for (int t = 0; t < NT; ++t)
+                        b[t] = buffer_frag<frag_t>(rsrc, vlane + (s + 1) * 64 * FB, t * KS * 64 * FB);
+                }
             }
         }
         wave_sync();  // every G read is done: the staging area reuses the rows
@@ -418,23 +440,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // then, in four passes of four cells, the waves write their accumulators
 // (both mirrored entries) into the staging area, which reuses the G rows'
 // LDS, and the workgroup copies those cells out as contiguous 16-byte stores.
-// Word 3 of a raw buffer resource on gfx9-family chips: 32-bit data format
-// (a zero format would make untyped buffer accesses read zeros).
-constexpr int kBufferWord3 = 0x00020000;
-
-// One MFMA fragment (8, 4 or 16 bytes) from a raw buffer.
-template <typename F>
-__device__ inline F buffer_frag(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    if constexpr (sizeof(F) == 4) {
-        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-    } else if constexpr (sizeof(F) == 8) {
-        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-    } else {
-        static_assert(sizeof(F) == 16, "fragment of 4, 8 or 16 bytes");
-        return __builtin_bit_cast(F, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
-    }
-}
-
 template <int FORM, int P, int FD, int PREC, int NQ>
 struct PrismBigCfg {
     using C = PrismCfg<FORM, P, FD, PREC, NQ>;
