@@ -213,6 +213,8 @@ def main(argv=None):
         entries += tune_linear("helmholtz_p1_prism", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 4), variants=(0,))
         entries += tune_linear("diffusion_p2_prism", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 3, 4, 8),
                                variants=(0,))
+        entries += tune_linear("diffusion_p3_prism", ("fp64", "fp32", "bf16x3"), candidates=(1, 2, 3, 4, 8),
+                               variants=(0,))
         mb = inputs.mixed_batch()
     else:
         mb = inputs.mixed_batch(n_tri=64, n_tet=12, tri_counts=(3000, 2000, 1500, 1000),
