@@ -433,27 +433,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // that the L2 evicts before they are complete, so the matrices go out through
 // a staging area, a few whole cells at a time.
 //
-// The four waves of a workgroup share one 16-cell tile: all 256 threads form
-// the tile's G rows in LDS once (16 threads per cell, each a sixteenth of the
-// points), each wave contracts them with its quarter of the n-tiles (the R
-// fragments of step s + 1 load from L2 during the products of step s), and
-// then, in four passes of four cells, the waves write their accumulators
-// (both mirrored entries) into the staging area, which reuses the G rows'
-// LDS, and the workgroup copies those cells out as contiguous 16-byte stores.
+// A workgroup of eight waves takes two 16-cell tiles (32 cells): all 512
+// threads form the 32 cells' G rows in LDS once (16 threads per cell, each a
+// sixteenth of the points), and each wave contracts both tiles' rows with an
+// eighth of the n-tiles, so that every R fragment loaded from L2 serves two
+// products (one fragment per product would ask the L2 for about 64 bytes per
+// clock per CU at the FP64 matrix-core rate, its whole bandwidth). The
+// fragments of step s + 1 load during the products of step s. Then, in eight
+// passes of four cells, the waves write their accumulators (both mirrored
+// entries) into the staging area, which reuses the G rows' LDS, and the
+// workgroup copies those cells out as contiguous 16-byte stores.
 template <int FORM, int P, int FD, int PREC, int NQ>
 struct PrismBigCfg {
     using C = PrismCfg<FORM, P, FD, PREC, NQ>;
-    static constexpr int WAVES = 4;
+    static constexpr int CT = 2;  // 16-cell tiles per workgroup
+    static constexpr int WAVES = 8;
     static constexpr int TCH = (C::NT + WAVES - 1) / WAVES;  // n-tiles per wave
-    static constexpr int GT_BYTES = 16 * C::ROW * (int)sizeof(typename C::g_t);
+    static constexpr int GT_BYTES = 16 * CT * C::ROW * (int)sizeof(typename C::g_t);
     static constexpr int ST_BYTES = 4 * C::NN * (int)sizeof(typename C::out_t);  // four cells
     static constexpr int LDS_BYTES = ((GT_BYTES > ST_BYTES ? GT_BYTES : ST_BYTES) + 15) / 16 * 16;
-    static_assert(LDS_BYTES <= 160 * 1024, "G rows and staging fit the LDS");
+    static_assert(LDS_BYTES + NQ * 32 <= 160 * 1024, "G rows, staging and the rule fit the LDS");
     static_assert(C::NN * (int)sizeof(typename C::out_t) % 16 == 0, "cell matrices of whole 16-byte vectors");
 };
 
 template <int FORM, int P, int FD, int PREC, int NQ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_prism_big(PrismArgs A) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_prism_big(PrismArgs A) {
     using C = PrismCfg<FORM, P, FD, PREC, NQ>;
     using B = PrismBigCfg<FORM, P, FD, PREC, NQ>;
     using g_t = typename C::g_t;
@@ -461,7 +465,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     using acc_t = typename C::acc_t;
     using out_t = typename C::out_t;
     constexpr int NS = C::NS, NN = C::NN, NU = C::NU, NT = C::NT, KS = C::KS, JQ = C::JQ, KR = C::KR,
-                  ROW = C::ROW, TCH = B::TCH;
+                  ROW = C::ROW, TCH = B::TCH, CT = B::CT;
+    constexpr int CELLS = 16 * CT;  // cells per workgroup tile
     extern __shared__ __attribute__((aligned(16))) char lds[];
     __shared__ double sq[NQ * 4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -499,15 +504,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             b[i] = buffer_frag<frag_t>(rsrc, vo, (unsigned)((t0 + i < NT ? i : NT - 1 - t0) * KS * 64) * FB);
     };
 
-    for (int64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
-        const int64_t base = tile * 16;
+    const int64_t ngroups = (A.ncells + CELLS - 1) / CELLS;
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int64_t base = grp * CELLS;
         __syncthreads();  // the previous tile's staging reads are done (and sq is loaded)
 
-        // G rows: thread (cell col, point group pg) forms points pg, pg + 16, ...
+        // G rows: thread (cell r, point group pg) forms points pg, pg + 16, ...
         {
-            const int col = tid & 15, pg = tid >> 4;
-            const bool valid = base + col < A.ncells;
-            const int64_t cell = valid ? base + col : A.ncells - 1;
+            const int r = tid % CELLS, pg = tid / CELLS;
+            constexpr int PG = 64 * B::WAVES / CELLS;  // point groups
+            const bool valid = base + r < A.ncells;
+            const int64_t cell = valid ? base + r : A.ncells - 1;
             PrismIdx ix;
             PrismRaw<FD> raw;
             prism_idx<FD>(A, cell, ix);
@@ -523,12 +530,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 e[5][i] = raw.x[3][i] - raw.x[2][i];
                 e[6][i] = raw.x[5][i] - raw.x[4][i];
             }
-            g_t* row = gt + col * ROW;
+            g_t* row = gt + r * ROW;
             // k padding past the G entries (the staging area overwrote it)
             constexpr int KFILL = PREC == PREC_BF16X3 ? 3 * KR : KR;
-            for (int k = KFILL + pg; k < KS * kstep(PREC); k += 16) row[k] = g_t(0);
+            for (int k = KFILL + pg; k < KS * kstep(PREC); k += PG) row[k] = g_t(0);
 #pragma unroll 1
-            for (int q = pg; q < NQ; q += 16) {
+            for (int q = pg; q < NQ; q += PG) {
                 const double X = sq[4 * q], Y = sq[4 * q + 1], Z = sq[4 * q + 2], W = sq[4 * q + 3];
                 const double zb = 1.0 - Z, l0 = 1.0 - X - Y;
                 double J[3][3];
@@ -565,37 +572,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         load_b(b, 0);
         __syncthreads();
 
-        // contraction of the 16 cells' G rows with this wave's n-tiles
-        acc_t acc[TCH];
+        // contraction of the two tiles' G rows with this wave's n-tiles (the G
+        // fragments of step s + 1 are read during the products of step s)
+        acc_t acc[CT][TCH];
 #pragma unroll
-        for (int i = 0; i < TCH; ++i) acc[i] = acc_t{0, 0, 0, 0};
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int i = 0; i < TCH; ++i) acc[c][i] = acc_t{0, 0, 0, 0};
+        frag_t a[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) a[c] = load_afrag<PREC>(gt + 16 * c * ROW, ROW, lane, 0);
 #pragma unroll 1
         for (int s = 0; s < KS; ++s) {
-            const frag_t a0 = load_afrag<PREC>(gt, ROW, lane, s);
+            frag_t an[CT];
 #pragma unroll
-            for (int i = 0; i < TCH; ++i) acc[i] = mfma<PREC>(a0, b[i], acc[i]);
+            for (int c = 0; c < CT; ++c) an[c] = load_afrag<PREC>(gt + 16 * c * ROW, ROW, lane, s + 1 < KS ? s + 1 : s);
+#pragma unroll
+            for (int i = 0; i < TCH; ++i)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) acc[c][i] = mfma<PREC>(a[c], b[i], acc[c][i]);
             if (s + 1 < KS) load_b(b, s + 1);  // in flight during these products
+#pragma unroll
+            for (int c = 0; c < CT; ++c) a[c] = an[c];
         }
 
-        // four passes: the cells of accumulator element v (slot = lane / 16)
+        // 4 CT passes: the cells of tile c and accumulator element v (slot = lane / 16)
         constexpr int NV1 = NN * (int)sizeof(out_t) / 16;  // 16-byte vectors per cell
         const u32x4p* s4 = reinterpret_cast<const u32x4p*>(st);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            __syncthreads();  // G reads (first pass) or the previous pass's copies are done
+        for (int c = 0; c < CT; ++c) {
 #pragma unroll
-            for (int i = 0; i < TCH; ++i) {
-                if (16 * (t0 + i) + (lane & 15) >= NU) continue;
-                const out_t x = (out_t)acc[i][v];
-                st[(lane >> 4) * NN + (off[i] & 0xffff)] = x;
-                st[(lane >> 4) * NN + (off[i] >> 16)] = x;
-            }
-            __syncthreads();
-            for (int k = tid; k < 4 * NV1; k += blockDim.x) {
-                const int slot = k / NV1;
-                const int64_t c = base + acc_row<PREC>(16 * slot, v);
-                if (c < A.ncells)
-                    gstore_nt(reinterpret_cast<u32x4p*>(out + c * NN) + (k - slot * NV1), s4[k]);
+            for (int v = 0; v < 4; ++v) {
+                __syncthreads();  // G reads (first pass) or the previous pass's copies are done
+#pragma unroll
+                for (int i = 0; i < TCH; ++i) {
+                    if (16 * (t0 + i) + (lane & 15) >= NU) continue;
+                    const out_t x = (out_t)acc[c][i][v];
+                    st[(lane >> 4) * NN + (off[i] & 0xffff)] = x;
+                    st[(lane >> 4) * NN + (off[i] >> 16)] = x;
+                }
+                __syncthreads();
+                for (int k = tid; k < 4 * NV1; k += blockDim.x) {
+                    const int slot = k / NV1;
+                    const int64_t cl = base + 16 * c + acc_row<PREC>(16 * slot, v);
+                    if (cl < A.ncells)
+                        gstore_nt(reinterpret_cast<u32x4p*>(out + cl * NN) + (k - slot * NV1), s4[k]);
+                }
             }
         }
     }
@@ -704,7 +726,7 @@ hipError_t launch_prism_big(const dev::PrismArgs& a, hipStream_t s, int dev_id) 
     static const hipError_t attr =
         hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, B::LDS_BYTES);
     if (attr != hipSuccess) return attr;
-    const int64_t wgs_needed = a.ntiles;  // one 16-cell tile per workgroup at a time
+    const int64_t wgs_needed = (a.ncells + 16 * B::CT - 1) / (16 * B::CT);  // one tile group per workgroup at a time
     int tuned_variant = 0;
     const int tuned = tuned_linear(FORM, COFFEE_PRISM, P, FD, PREC, &tuned_variant);
     const int grid = grid_for(dev_id, kern, B::WAVES * 64, B::LDS_BYTES, wgs_needed, tuned > 0 ? tuned : 1);
