@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // A workgroup of eight waves takes two 16-cell tiles (32 cells): all 512
 // threads form the 32 cells' G rows in LDS once (16 threads per cell, each a
 // sixteenth of the points), and each wave contracts both tiles' rows with an
-// eighth of the n-tiles, so that every R fragment loaded from L2 serves two
+// eighth of the n-tiles (6 or 7 of 52 at degree 3), so that every R fragment loaded from L2 serves two
 // products (one fragment per product would ask the L2 for about 64 bytes per
 // clock per CU at the FP64 matrix-core rate, its whole bandwidth). The
 // fragments of step s + 1 load during the products of step s. Then, in eight
@@ -448,7 +448,16 @@ struct PrismBigCfg {
     using C = PrismCfg<FORM, P, FD, PREC, NQ>;
     static constexpr int CT = 2;  // 16-cell tiles per workgroup
     static constexpr int WAVES = 8;
-    static constexpr int TCH = (C::NT + WAVES - 1) / WAVES;  // n-tiles per wave
+    // n-tiles per wave. FP64/FP32: the first NT % WAVES waves take one more
+    // (waves w and w + 4 share a SIMD, so each SIMD gets an equal share when
+    // NT % WAVES <= 4), with no tile computed twice. BF16X3 (short products,
+    // where the per-tile branches cost more than they save): TCH tiles on
+    // every wave, tiles past NT repeating the last one, their products never
+    // stored.
+    static constexpr bool BAL = PREC != PREC_BF16X3;
+    static constexpr int TB = BAL ? C::NT / WAVES : (C::NT + WAVES - 1) / WAVES;
+    static constexpr int TR = BAL ? C::NT % WAVES : 0;
+    static constexpr int TCH = TB + (TR ? 1 : 0);
     static constexpr int GT_BYTES = 16 * CT * C::ROW * (int)sizeof(typename C::g_t);
     static constexpr int ST_BYTES = 4 * C::NN * (int)sizeof(typename C::out_t);  // four cells
     static constexpr int LDS_BYTES = ((GT_BYTES > ST_BYTES ? GT_BYTES : ST_BYTES) + 15) / 16 * 16;
@@ -474,7 +483,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     out_t* st = reinterpret_cast<out_t*>(lds);
     const frag_t* rf = reinterpret_cast<const frag_t*>(A.rfrag);
     out_t* out = reinterpret_cast<out_t*>(A.out);
-    const int t0 = __builtin_amdgcn_readfirstlane(wave) * TCH;  // this wave's n-tiles t0 .. t0 + TCH - 1 (scalar)
+    // this wave's n-tiles t0 .. t0 + ntw - 1 (scalars)
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int t0 = wv * B::TB + (wv < B::TR ? wv : B::TR);
+    const int ntw = B::TB + (wv < B::TR ? 1 : 0);
 
     // staging offsets of this lane's unique entries u = 16 t + (lane & 15):
     // (a, b), a <= b, row-major over the upper triangle (low half), and its
@@ -492,8 +504,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     for (int i = tid; i < NQ * 4; i += blockDim.x) sq[i] = gload(A.qtab + i);
     // the R fragments of this wave's n-tiles at k-step g, as buffer loads: the
-    // lane's offset in one register, each tile's offset a scalar (tiles past
-    // NT repeat the last one; their products are never stored)
+    // lane's offset in one register, each tile's offset a scalar
     constexpr unsigned FB = sizeof(frag_t);
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<frag_t*>(rf), (short)0, NT * KS * 64 * (int)FB, kBufferWord3);
@@ -501,7 +512,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
         const unsigned vo = ((unsigned)(t0 * KS + g) * 64 + lane) * FB;
 #pragma unroll
         for (int i = 0; i < TCH; ++i)
-            b[i] = buffer_frag<frag_t>(rsrc, vo, (unsigned)((t0 + i < NT ? i : NT - 1 - t0) * KS * 64) * FB);
+            if (i < ntw)
+                b[i] = buffer_frag<frag_t>(rsrc, vo, (unsigned)((B::BAL || t0 + i < NT ? i : NT - 1 - t0) * KS * 64) * FB);
     };
 
     const int64_t ngroups = (A.ncells + CELLS - 1) / CELLS;
@@ -589,8 +601,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int c = 0; c < CT; ++c) an[c] = load_afrag<PREC>(gt + 16 * c * ROW, ROW, lane, s + 1 < KS ? s + 1 : s);
 #pragma unroll
             for (int i = 0; i < TCH; ++i)
+                if (i < ntw) {
 #pragma unroll
-                for (int c = 0; c < CT; ++c) acc[c][i] = mfma<PREC>(a[c], b[i], acc[c][i]);
+                    for (int c = 0; c < CT; ++c) acc[c][i] = mfma<PREC>(a[c], b[i], acc[c][i]);
+                }
             if (s + 1 < KS) load_b(b, s + 1);  // in flight during these products
 #pragma unroll
             for (int c = 0; c < CT; ++c) a[c] = an[c];
@@ -606,7 +620,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                 __syncthreads();  // G reads (first pass) or the previous pass's copies are done
 #pragma unroll
                 for (int i = 0; i < TCH; ++i) {
-                    if (16 * (t0 + i) + (lane & 15) >= NU) continue;
+                    if (i >= ntw || 16 * (t0 + i) + (lane & 15) >= NU) continue;
                     const out_t x = (out_t)acc[c][i][v];
                     st[(lane >> 4) * NN + (off[i] & 0xffff)] = x;
                     st[(lane >> 4) * NN + (off[i] >> 16)] = x;
