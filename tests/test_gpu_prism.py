@@ -72,7 +72,7 @@ def test_prism_vs_oracle(cf, oracle, form, kind, p, prec):
     assert err < TOL[prec]
 
 
-@pytest.mark.parametrize("ncells", [1, 15, 16, 17, 33, 250])
+@pytest.mark.parametrize("ncells", [1, 15, 16, 17, 31, 32, 33, 64, 250])
 def test_prism_ragged_counts(cf, oracle, ncells):
     """Cell counts around the 16-cell tile: the first ncells cells of a mesh."""
     from gpu_util import assemble_gpu, cell_rel_err
