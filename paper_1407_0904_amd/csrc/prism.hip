@@ -447,7 +447,9 @@ template <int FORM, int P, int FD, int PREC, int NQ>
 struct PrismBigCfg {
     using C = PrismCfg<FORM, P, FD, PREC, NQ>;
     static constexpr int CT = 2;  // 16-cell tiles per workgroup
-    static constexpr int WAVES = 8;
+    // eight waves at degree 3 (52 n-tiles); four at degree 2 (11 n-tiles:
+    // three per wave, so that each G fragment read feeds six products)
+    static constexpr int WAVES = P >= 3 ? 8 : 4;
     // n-tiles per wave. FP64/FP32: the first NT % WAVES waves take one more
     // (waves w and w + 4 share a SIMD, so each SIMD gets an equal share when
     // NT % WAVES <= 4), with no tile computed twice. BF16X3 (short products,
@@ -751,7 +753,7 @@ hipError_t launch_prism_big(const dev::PrismArgs& a, hipStream_t s, int dev_id) 
 
 template <int FORM, int P, int FD, int NQ>
 hipError_t launch_prism_prec(int prec, const dev::PrismArgs& a, hipStream_t s, int dev_id) {
-    if constexpr (P >= 3) {
+    if constexpr (P >= 2) {
         if (prec == COFFEE_FP64) return launch_prism_big<FORM, P, FD, dev::PREC_F64, NQ>(a, s, dev_id);
         if (prec == COFFEE_FP32) return launch_prism_big<FORM, P, FD, dev::PREC_F32, NQ>(a, s, dev_id);
         return launch_prism_big<FORM, P, FD, dev::PREC_BF16X3, NQ>(a, s, dev_id);
