@@ -439,10 +439,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // eighth of the n-tiles (6 or 7 of 52 at degree 3), so that every R fragment loaded from L2 serves two
 // products (one fragment per product would ask the L2 for about 64 bytes per
 // clock per CU at the FP64 matrix-core rate, its whole bandwidth). The
-// fragments of step s + 1 load during the products of step s. Then, in eight
-// passes of four cells, the waves write their accumulators (both mirrored
-// entries) into the staging area, which reuses the G rows' LDS, and the
-// workgroup copies those cells out as contiguous 16-byte stores.
+// fragments of step s + 1 load during the products of step s. Then, in passes
+// of as many cells as fit in the G rows' LDS (four at degree 3, sixteen at
+// degree 2), the waves write their accumulators (both mirrored entries) into
+// that staging area, and the workgroup copies those cells out as contiguous
+// 16-byte stores.
 template <int FORM, int P, int FD, int PREC, int NQ>
 struct PrismBigCfg {
     using C = PrismCfg<FORM, P, FD, PREC, NQ>;
@@ -461,7 +462,14 @@ struct PrismBigCfg {
     static constexpr int TR = BAL ? C::NT % WAVES : 0;
     static constexpr int TCH = TB + (TR ? 1 : 0);
     static constexpr int GT_BYTES = 16 * CT * C::ROW * (int)sizeof(typename C::g_t);
-    static constexpr int ST_BYTES = 4 * C::NN * (int)sizeof(typename C::out_t);  // four cells
+    // cells per staging pass: the most (4, 8, 16 or 32) whose matrices fit in
+    // the G rows' LDS, at least four
+    static constexpr int CB = C::NN * (int)sizeof(typename C::out_t);
+    static constexpr int PC = 32 * CB <= GT_BYTES && CT == 2   ? 32
+                              : 16 * CB <= GT_BYTES             ? 16
+                              : 8 * CB <= GT_BYTES              ? 8
+                                                                : 4;
+    static constexpr int ST_BYTES = PC * CB;
     static constexpr int LDS_BYTES = ((GT_BYTES > ST_BYTES ? GT_BYTES : ST_BYTES) + 15) / 16 * 16;
     static_assert(LDS_BYTES + NQ * 32 <= 160 * 1024, "G rows, staging and the rule fit the LDS");
     static_assert(C::NN * (int)sizeof(typename C::out_t) % 16 == 0, "cell matrices of whole 16-byte vectors");
@@ -612,28 +620,33 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int c = 0; c < CT; ++c) a[c] = an[c];
         }
 
-        // 4 CT passes: the cells of tile c and accumulator element v (slot = lane / 16)
+        // 4 CT / NVP passes. Pass p holds the NVP (tile c, accumulator element
+        // v) pairs j = p NVP .. p NVP + NVP - 1, c = j / 4, v = j % 4; staging
+        // slot 4 jj + lane / 16 is the cell of pair jj held by lane group
+        // lane / 16.
+        constexpr int NVP = B::PC / 4;
         constexpr int NV1 = NN * (int)sizeof(out_t) / 16;  // 16-byte vectors per cell
         const u32x4p* s4 = reinterpret_cast<const u32x4p*>(st);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
+        for (int p = 0; p < 4 * CT / NVP; ++p) {
+            __syncthreads();  // G reads (first pass) or the previous pass's copies are done
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                __syncthreads();  // G reads (first pass) or the previous pass's copies are done
+            for (int jj = 0; jj < NVP; ++jj) {
+                const int c = (p * NVP + jj) / 4, v = (p * NVP + jj) % 4;
 #pragma unroll
                 for (int i = 0; i < TCH; ++i) {
                     if (i >= ntw || 16 * (t0 + i) + (lane & 15) >= NU) continue;
                     const out_t x = (out_t)acc[c][i][v];
-                    st[(lane >> 4) * NN + (off[i] & 0xffff)] = x;
-                    st[(lane >> 4) * NN + (off[i] >> 16)] = x;
+                    st[(4 * jj + (lane >> 4)) * NN + (off[i] & 0xffff)] = x;
+                    st[(4 * jj + (lane >> 4)) * NN + (off[i] >> 16)] = x;
                 }
-                __syncthreads();
-                for (int k = tid; k < 4 * NV1; k += blockDim.x) {
-                    const int slot = k / NV1;
-                    const int64_t cl = base + 16 * c + acc_row<PREC>(16 * slot, v);
-                    if (cl < A.ncells)
-                        gstore_nt(reinterpret_cast<u32x4p*>(out + cl * NN) + (k - slot * NV1), s4[k]);
-                }
+            }
+            __syncthreads();
+            for (int k = tid; k < B::PC * NV1; k += blockDim.x) {
+                const int slot = k / NV1, j = p * NVP + slot / 4;
+                const int64_t cl = base + 16 * (j / 4) + acc_row<PREC>(16 * (slot % 4), j % 4);
+                if (cl < A.ncells)
+                    gstore_nt(reinterpret_cast<u32x4p*>(out + cl * NN) + (k - slot * NV1), s4[k]);
             }
         }
     }
