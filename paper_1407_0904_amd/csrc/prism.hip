@@ -642,11 +642,27 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                 }
             }
             __syncthreads();
-            for (int k = tid; k < B::PC * NV1; k += blockDim.x) {
-                const int slot = k / NV1, j = p * NVP + slot / 4;
-                const int64_t cl = base + 16 * (j / 4) + acc_row<PREC>(16 * (slot % 4), j % 4);
-                if (cl < A.ncells)
-                    gstore_nt(reinterpret_cast<u32x4p*>(out + cl * NN) + (k - slot * NV1), s4[k]);
+            if constexpr (NVP >= 4) {
+                // whole tiles: the pass's cells are contiguous, copied in
+                // memory order (lines shared by neighbouring cells are then
+                // written together); cell r of a tile sits in the slot of
+                // its (lane group, v)
+                const int64_t c0 = base + 16 * (p * NVP / 4);
+                for (int k = tid; k < B::PC * NV1; k += blockDim.x) {
+                    const int lc = k / NV1, r = lc % 16;
+                    const int g = PREC == PREC_F64 ? r % 4 : r / 4, v = PREC == PREC_F64 ? r / 4 : r % 4;
+                    const int slot = 4 * (4 * (lc / 16) + v) + g;
+                    if (c0 + lc < A.ncells)
+                        gstore_nt(reinterpret_cast<u32x4p*>(out + (c0 + lc) * NN) + (k - lc * NV1),
+                                  s4[slot * NV1 + (k - lc * NV1)]);
+                }
+            } else {
+                for (int k = tid; k < B::PC * NV1; k += blockDim.x) {
+                    const int slot = k / NV1, j = p * NVP + slot / 4;
+                    const int64_t cl = base + 16 * (j / 4) + acc_row<PREC>(16 * (slot % 4), j % 4);
+                    if (cl < A.ncells)
+                        gstore_nt(reinterpret_cast<u32x4p*>(out + cl * NN) + (k - slot * NV1), s4[k]);
+                }
             }
         }
     }
