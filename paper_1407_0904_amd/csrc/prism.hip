@@ -17,12 +17,14 @@
 // the matrices are symmetric), on the same MFMA instructions as the simplex
 // engines (linear.hpp).
 //
-// Per wave: one tile of 16 cells at a time. The 64 lanes are 16 cells x 4
-// groups of quadrature points: each lane gathers its cell (all four lanes of
-// a cell read the same lines), forms J, K and |det J| in FP64 at its points
-// and writes those G entries to the tile's LDS rows. The MFMA loop then runs
-// over all n-tiles at once, and the 16 element matrices leave through LDS as
-// contiguous 16-byte stores (the staging area reuses the G rows).
+// Degree 1 (k_prism), per wave: one tile of 16 cells at a time. The 64
+// lanes are 16 cells x 4 groups of quadrature points: each lane gathers its
+// cell (all four lanes of a cell read the same lines), forms J, K and |det J|
+// in FP64 at its points and writes those G entries to the tile's LDS rows.
+// The MFMA loop then runs over all n-tiles at once, and the 16 element
+// matrices leave through LDS as contiguous 16-byte stores (the staging area
+// reuses the G rows). Degrees 2 and 3 (k_prism_big): the waves of a
+// workgroup share 32 cells, each wave taking a share of the n-tiles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -423,9 +425,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (tile < A.ntiles) tile_body(std::integral_constant<bool, false>());
 }
 
-
-
-// ---------------------------------------------------------------- degree >= 3
+// ---------------------------------------------------------------- degrees 2, 3
 // At degree 3 (40 dofs, 820 unique entries in 52 n-tiles, 64 points, K = 448
 // for Helmholtz) one wave cannot hold the accumulators of all n-tiles, and 16
 // cells' matrices (205 KB in FP64) are larger than the LDS. A cell's matrix
@@ -433,12 +433,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // that the L2 evicts before they are complete, so the matrices go out through
 // a staging area, a few whole cells at a time.
 //
-// A workgroup of eight waves takes two 16-cell tiles (32 cells): all 512
-// threads form the 32 cells' G rows in LDS once (16 threads per cell, each a
-// sixteenth of the points), and each wave contracts both tiles' rows with an
-// eighth of the n-tiles (6 or 7 of 52 at degree 3), so that every R fragment loaded from L2 serves two
-// products (one fragment per product would ask the L2 for about 64 bytes per
-// clock per CU at the FP64 matrix-core rate, its whole bandwidth). The
+// A workgroup takes two 16-cell tiles (32 cells): all its threads form the
+// 32 cells' G rows in LDS once (each thread one cell and a share of the
+// points), and each wave contracts both tiles' rows with its share of the
+// n-tiles, so that every R fragment loaded from L2 serves two products (one
+// fragment per product would ask the L2 for about 64 bytes per clock per CU
+// at the FP64 matrix-core rate, its whole bandwidth). Degree 3 runs eight
+// waves (6 or 7 of the 52 n-tiles each), degree 2 four (2 or 3 of 11). The
 // fragments of step s + 1 load during the products of step s. Then, in passes
 // of as many cells as fit in the G rows' LDS (four at degree 3, sixteen at
 // degree 2), the waves write their accumulators (both mirrored entries) into
