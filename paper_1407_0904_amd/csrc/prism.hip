@@ -605,8 +605,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
         frag_t a[CT];
 #pragma unroll
         for (int c = 0; c < CT; ++c) a[c] = load_afrag<PREC>(gt + 16 * c * ROW, ROW, lane, 0);
-#pragma unroll 1
-        for (int s = 0; s < KS; ++s) {
+        // one k-step: the products of step s with R fragments bc, the G
+        // fragments of step s + 1 read meanwhile; R fragments of step s + 1
+        // into bn (issued before the products when bn is a second buffer,
+        // after them when it is bc itself)
+        auto step = [&](int s, frag_t* bc, frag_t* bn) {
+            if (bn != bc && s + 1 < KS) load_b(bn, s + 1);
             frag_t an[CT];
 #pragma unroll
             for (int c = 0; c < CT; ++c) an[c] = load_afrag<PREC>(gt + 16 * c * ROW, ROW, lane, s + 1 < KS ? s + 1 : s);
@@ -614,11 +618,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int i = 0; i < TCH; ++i)
                 if (i < ntw) {
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) acc[c][i] = mfma<PREC>(a[c], b[i], acc[c][i]);
+                    for (int c = 0; c < CT; ++c) acc[c][i] = mfma<PREC>(a[c], bc[i], acc[c][i]);
                 }
-            if (s + 1 < KS) load_b(b, s + 1);  // in flight during these products
+            if (bn == bc && s + 1 < KS) load_b(bc, s + 1);
 #pragma unroll
             for (int c = 0; c < CT; ++c) a[c] = an[c];
+        };
+        if constexpr (B::BAL) {
+            // FP64/FP32: two R buffers (BF16X3's short products were slower so)
+            frag_t b1[TCH];
+#pragma unroll 1
+            for (int s = 0; s < KS; s += 2) {
+                step(s, b, b1);
+                if (s + 1 < KS) step(s + 1, b1, b);
+            }
+        } else {
+#pragma unroll 1
+            for (int s = 0; s < KS; ++s) step(s, b, b);
         }
 
         // 4 CT / NVP passes. Pass p holds the NVP (tile c, accumulator element
